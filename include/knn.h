@@ -1,0 +1,138 @@
+/*
+ * knn.h -- C ABI of the brute-force k-nearest-neighbour library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation (Garcia, Debreuve, Barlaud, "Fast k Nearest Neighbor Search
+ * using GPU", Section 2.1, problem definition): given m reference points
+ * R = {r_0..r_{m-1}} and n query points Q = {q_0..q_{n-1}} in d dimensions,
+ * return for every query the k references nearest to it under a given
+ * distance.  The method is the brute force of the same section: every one of
+ * the n*m distances is computed, and the k smallest are kept per query.  The
+ * library fuses the two steps: the n*m distance matrix never reaches device
+ * memory.
+ *
+ * Conventions for every entry point:
+ *   - Points are float32, row-major, one point per row: Q is [n][d], R is
+ *     [m][d], contiguous.  Outputs are dist [n][k] float32 and idx [n][k]
+ *     int32, row-major.
+ *   - Q, R, dist and idx are DEVICE pointers owned by the caller, unless an
+ *     entry point says otherwise.  They must stay valid until the work
+ *     enqueued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on it and return without waiting.  Argument errors
+ *     are detected before anything is enqueued; the outputs are then left
+ *     untouched.  A device failure is reported as KNN_ERR_DEVICE by the call
+ *     that observes it.
+ *   - Indices are 0-based.  Row i of the result lists the k nearest
+ *     references of q_i by increasing distance; equal distances are ordered
+ *     by increasing reference index.
+ *   - Euclidean results are the distance itself (square root of the sum of
+ *     squared differences), not its square.
+ *   - Requirements: n >= 0 (n == 0 is a no-op), m >= 1, d >= 1,
+ *     1 <= k <= m (k == m returns every reference).
+ *   - Inputs containing NaN or infinity are outside the contract.
+ *   - Handles are not thread-safe; distinct handles may be used from
+ *     distinct threads.
+ *   - knn_last_error() returns a thread-local message for the last non-OK
+ *     status returned on the calling thread.
+ */
+#ifndef KNN_H
+#define KNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Distances named in Section 2.1: Euclidean, Manhattan, infinity norm. */
+enum knn_metric { KNN_L2 = 0, KNN_L1 = 1, KNN_LINF = 2 };
+
+/* Arithmetic of the distance tiles.  KNN_FP32 computes in float32.
+ * KNN_BF16 / KNN_FP16 round the points to bfloat16 / float16 (round to
+ * nearest even) for the Euclidean cross term on the matrix cores with float32
+ * accumulation; the kept candidates are then re-ranked with exact float32
+ * differences.  The low-precision forms support KNN_L2 only. */
+enum knn_precision { KNN_FP32 = 0, KNN_BF16 = 1, KNN_FP16 = 2 };
+
+enum knn_status {
+  KNN_OK = 0,
+  KNN_ERR_INVALID = -1,     /* bad argument (null pointer, k out of range, ...) */
+  KNN_ERR_UNSUPPORTED = -2, /* valid request the library does not implement    */
+  KNN_ERR_OOM = -3,         /* device or host memory exhausted                 */
+  KNN_ERR_DEVICE = -4,      /* a HIP call failed                               */
+  KNN_ERR_BUSY = -5         /* serving back-pressure: retry later              */
+};
+
+typedef struct knn_refs_s* knn_refs_t; /* opaque, owned by the library */
+
+/* Library version, major*10000 + minor*100 + patch. */
+int knn_version(void);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* knn_last_error(void);
+
+/*
+ * knn_search -- one-shot brute force, float32 arithmetic (Section 2.1).
+ *   Q [n][d], R [m][d]: device float32 inputs.
+ *   dist [n][k], idx [n][k]: device outputs.
+ *   metric: enum knn_metric.
+ * Equivalent to knn_create_refs + knn_search_refs(precision KNN_FP32) +
+ * knn_destroy_refs, but without keeping a copy of R: the reference
+ * preparation (padding, squared norms) runs inside the call, in a
+ * library-owned per-stream workspace that grows on demand.
+ * Errors: KNN_ERR_INVALID for bad arguments, KNN_ERR_OOM if the workspace
+ * cannot grow, KNN_ERR_DEVICE if a launch fails.
+ */
+int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, int32_t k,
+               int32_t metric, float* dist, int32_t* idx, void* stream);
+
+/*
+ * knn_create_refs -- prepare a resident reference set (the reference side of
+ * the distance computation of Section 2.1, done once).
+ *   R [m][d]: device float32 input; it is copied, so the caller may free it
+ *     once the work on `stream` has completed.
+ *   storage: enum knn_precision of the rows kept for the distance tiles.
+ *     KNN_FP32 keeps float32 rows; KNN_BF16 / KNN_FP16 keep rows rounded to
+ *     nearest even, plus float32 squared norms of the rounded rows.
+ *   keep_fp32_master: for KNN_BF16 / KNN_FP16 storage, non-zero also keeps
+ *     the float32 rows, which the exact re-rank then reads; zero makes the
+ *     rounded rows canonical (the re-rank upcasts them exactly).
+ *   out: receives the handle.
+ * Errors: KNN_ERR_INVALID, KNN_ERR_OOM, KNN_ERR_DEVICE.
+ */
+int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage,
+                    int32_t keep_fp32_master, void* stream, knn_refs_t* out);
+
+/* Release a handle and its device memory (waits for the device first). */
+int knn_destroy_refs(knn_refs_t refs);
+
+/* Shape of a handle: any output pointer may be NULL. */
+int knn_refs_info(knn_refs_t refs, int64_t* m, int32_t* d, int32_t* storage,
+                  int32_t* has_fp32_master);
+
+/*
+ * knn_search_refs -- brute force against a resident set.
+ *   Q [n][d] device float32, same d as the set.
+ *   precision: enum knn_precision of the distance tiles; KNN_FP32 needs
+ *     float32 rows (storage KNN_FP32), KNN_BF16 / KNN_FP16 need rows stored
+ *     in that precision.
+ *   s_extra: candidates kept beyond k for the exact re-rank (k' = k + s_extra,
+ *     capped at m); negative selects the default (8 for KNN_FP32, 32 for the
+ *     low-precision forms).
+ *   dist/idx: device outputs [n][k].
+ * The distances returned are always exact float32 differences of the
+ * canonical rows (float32 master if kept, else the stored rows), whatever
+ * `precision` was used to rank candidates.
+ * Errors: KNN_ERR_INVALID, KNN_ERR_UNSUPPORTED (precision/storage/metric
+ * combination not available), KNN_ERR_OOM, KNN_ERR_DEVICE.
+ */
+int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32_t metric,
+                    int32_t precision, int32_t s_extra, float* dist, int32_t* idx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNN_H */

@@ -1,0 +1,61 @@
+"""ctypes loader for ``libknn.so`` (the C ABI declared in include/knn.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libknn.so")
+
+KNN_OK = 0
+STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BUSY"}
+METRICS = {"l2": 0, "l1": 1, "linf": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+# name -> (restype, argtypes); every symbol include/knn.h declares
+_c = ctypes
+SIGNATURES = {
+    "knn_version": (_c.c_int, []),
+    "knn_last_error": (_c.c_char_p, []),
+    "knn_search": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32,
+                              _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "knn_create_refs": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
+                                   _c.POINTER(_c.c_void_p)]),
+    "knn_destroy_refs": (_c.c_int, [_c.c_void_p]),
+    "knn_refs_info": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int32),
+                                 _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "knn_search_refs": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32,
+                                   _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+}
+
+
+class KnnError(RuntimeError):
+    """A non-OK status from the library, with its message."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0804_1448_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != KNN_OK:
+        msg = load().knn_last_error().decode(errors="replace")
+        raise KnnError(status, msg)

@@ -1,0 +1,95 @@
+// knn_internal.h -- types shared by the host dispatch (knn_api.cpp) and the
+// HIP kernels (knn_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace knn {
+
+// Selection keys: a candidate (score, reference index) is packed into one
+// 64-bit integer whose unsigned order is the lexicographic (score, index)
+// order: the high word is the score's IEEE bits mapped to a monotone
+// unsigned code, the low word the index.  An all-ones key marks an empty
+// slot and sorts after every real candidate.
+constexpr uint64_t kEmptyKey = ~0ull;
+
+// Distance tile kinds.
+enum TileKind : int {
+  TILE_L2_F32 = 0,   // Euclidean cross term on MFMA, float32 operands
+  TILE_L2_BF16 = 1,  // Euclidean cross term on MFMA, bfloat16 operands
+  TILE_L2_F16 = 2,   // Euclidean cross term on MFMA, float16 operands
+  TILE_L1_F32 = 3,   // Manhattan on the vector ALUs
+  TILE_LINF_F32 = 4, // infinity norm on the vector ALUs
+};
+
+// Storage element types of a prepared point array.
+enum ElemType : int { ELEM_F32 = 0, ELEM_BF16 = 1, ELEM_F16 = 2 };
+
+// Fixed geometry of the fused distance + selection kernel.
+constexpr int kWaveSize = 64;
+constexpr int kQueriesPerWave = 32;   // one MFMA 32x32 output column per query
+constexpr int kSubTiles = 2;          // 32-reference sub-tiles per step
+constexpr int kStepRefs = 32 * kSubTiles;  // references scored per step
+constexpr int kMaxMergePerLane = 8;   // (list + buffer) <= 64 * 8 keys
+constexpr int kMaxQChunkF32 = 128;    // float32 dims held in registers per chunk
+constexpr int kMaxQChunk16 = 256;     // 16-bit dims held in registers per chunk
+constexpr int kLdsBytes = 160 * 1024; // LDS per compute unit on gfx950
+
+// Parameters of the fused distance + top-k' selection kernel.
+struct FusedParams {
+  const void* Q;        // prepared queries [n][ldq] (element type of the tile kind)
+  const void* R;        // prepared references [m][ldr]
+  const float* rhalf;   // 0.5 * squared norm of each prepared reference (L2 only)
+  uint64_t* part;       // out: per-slice sorted candidate lists [n][P][kc]
+  int64_t n;
+  int64_t m;
+  int64_t slice_len;    // references per slice (multiple of kStepRefs)
+  int ldq;              // row stride of Q, elements
+  int ldr;              // row stride of R, elements
+  int dp;               // padded dimension (multiple of the MFMA k group)
+  int cw;               // dimensions per chunk (the last chunk may be shorter)
+  int nchunk;           // ceil(dp / cw)
+  int rstride;          // LDS row stride of a staged reference tile, elements
+  int P;                // number of slices
+  int kc;               // list capacity = k'
+  int cb;               // candidate buffer capacity per query
+  int waves;            // waves per workgroup
+};
+
+// Parameters of the merge + exact re-rank + finalize kernel.
+struct FinalParams {
+  const uint64_t* part; // [n][P][kc] sorted candidate lists (empty slots = kEmptyKey)
+  const float* Q;       // original float32 queries [n][ldq]
+  const void* Rm;       // canonical reference rows [m][ldr] (float32 or float16)
+  float* dist;          // out [n][k]
+  int32_t* idx;         // out [n][k]
+  int64_t n;
+  int64_t m;            // number of references (bounds every candidate index)
+  int ldq;
+  int ldr;
+  int rm_type;          // ElemType of Rm
+  int d;
+  int P;
+  int kc;
+  int kprime;           // candidates re-ranked (<= P * kc)
+  int k;
+  int metric;           // 0 L2, 1 L1, 2 Linf
+};
+
+constexpr int kFinalWaves = 4;          // queries per finalize workgroup
+constexpr int kFinalMaxKeys = 2048;     // P * kc limit of one finalize wave
+constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
+
+// Launchers (knn_kernels.hip).  All enqueue on `stream` and return the HIP
+// status of the launch.
+hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst,
+                            int ldd, int elem, float* rhalf, hipStream_t stream);
+int centre_partials(int64_t rows);  // partial sums launch_centre needs (times d floats)
+hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* partial, float* centre,
+                         hipStream_t stream);
+size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw);
+hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream);
+hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
+
+}  // namespace knn

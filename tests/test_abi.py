@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(knn_[a-z0-9_]+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_0804_1448_amd._lib as L
+
+    if not os.path.exists(L.LIB_PATH):
+        import paper_0804_1448_amd.build as B
+
+        B.build()
+    return L.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("knn_search", "knn_create_refs", "knn_search_refs", "knn_destroy_refs", "knn_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    import paper_0804_1448_amd._lib as L
+
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, f"binding lacks a signature for {name}"
+
+
+def test_version(lib):
+    assert lib.knn_version() >= 100
+
+
+P = ctypes.c_void_p
+FAKE = P(0x1000)  # never dereferenced: validation fails first
+
+
+def _search(lib, Q=FAKE, n=4, R=FAKE, m=10, d=3, k=2, metric=0, dist=FAKE, idx=FAKE):
+    return lib.knn_search(Q, n, R, m, d, k, metric, dist, idx, None)
+
+
+@pytest.mark.parametrize("kw,what", [
+    (dict(k=0), "k"), (dict(k=11), "k"), (dict(k=-3), "k"), (dict(d=0), "d"), (dict(m=0), "m"),
+    (dict(n=-1), "n"), (dict(metric=3), "metric"), (dict(Q=P(None)), "Q"), (dict(R=P(None)), "R"),
+    (dict(dist=P(None)), "dist"), (dict(idx=P(None)), "idx"),
+])
+def test_search_rejects_bad_arguments(lib, kw, what):
+    assert _search(lib, **kw) == -1
+    assert what in lib.knn_last_error().decode()
+
+
+def test_search_n_zero_is_noop(lib):
+    assert _search(lib, n=0, Q=P(None), dist=P(None), idx=P(None)) == 0
+
+
+def test_refs_calls_reject_bad_handles(lib):
+    assert lib.knn_destroy_refs(None) == -1
+    assert lib.knn_refs_info(None, None, None, None, None) == -1
+    assert lib.knn_search_refs(None, FAKE, 4, 2, 0, 0, -1, FAKE, FAKE, None) == -1
+
+
+def test_create_refs_rejects_bad_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.knn_create_refs(FAKE, 0, 3, 0, 1, None, ctypes.byref(h)) == -1
+    assert lib.knn_create_refs(FAKE, 10, 0, 0, 1, None, ctypes.byref(h)) == -1
+    assert lib.knn_create_refs(FAKE, 10, 3, 7, 1, None, ctypes.byref(h)) == -1
+    assert lib.knn_create_refs(P(None), 10, 3, 0, 1, None, ctypes.byref(h)) == -1
+    assert lib.knn_create_refs(FAKE, 10, 3, 0, 1, None, None) == -1
+    assert not h.value
+
+
+def test_last_error_is_thread_local(lib):
+    import threading
+
+    _search(lib, k=0)
+    seen = {}
+
+    def other():
+        seen["msg"] = lib.knn_last_error().decode()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == ""
+    assert "k" in lib.knn_last_error().decode()
