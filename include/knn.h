@@ -131,6 +131,22 @@ int knn_refs_info(knn_refs_t refs, int64_t* m, int32_t* d, int32_t* storage,
 int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32_t metric,
                     int32_t precision, int32_t s_extra, float* dist, int32_t* idx, void* stream);
 
+/*
+ * Kernel timing with HIP events (a measurement aid, not part of the method).
+ *   knn_timing_enable(1): every later launch of the library records a start
+ *     and a stop event on the stream it is launched on; (0) stops recording.
+ *   knn_timing_read(name, total_ms, launches): waits for the recorded events,
+ *     folds them into per-kernel totals and returns the summed duration (ms)
+ *     and launch count of kernel family `name`: "centre", "prep_refs",
+ *     "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
+ *     "fused_l1_f32", "fused_linf_f32", "finalize".  Unknown names read 0.
+ *   knn_timing_reset(): waits for and discards everything recorded.
+ * Errors: KNN_ERR_INVALID (NULL name), KNN_ERR_DEVICE.
+ */
+int knn_timing_enable(int32_t enable);
+int knn_timing_read(const char* name, double* total_ms, int64_t* launches);
+int knn_timing_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,33 @@ import torch
 
 from ._lib import METRICS, PRECISIONS, KnnError, check, load
 
-__all__ = ["search", "Refs", "KnnError", "METRICS", "PRECISIONS", "load"]
+__all__ = ["search", "Refs", "KnnError", "METRICS", "PRECISIONS", "load", "timing"]
+
+KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
+           "fused_l1_f32", "fused_linf_f32", "finalize")
+
+
+class timing:
+    """Per-kernel HIP-event timing inside the library (knn_timing_*)."""
+
+    @staticmethod
+    def enable(on: bool = True):
+        check(load().knn_timing_enable(int(on)))
+
+    @staticmethod
+    def reset():
+        check(load().knn_timing_reset())
+
+    @staticmethod
+    def read(name: str):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        check(load().knn_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    @staticmethod
+    def all():
+        return {k: timing.read(k) for k in KERNELS if timing.read(k)[1] > 0}
 
 
 def _stream_ptr(stream):

@@ -26,6 +26,9 @@ SIGNATURES = {
                                  _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "knn_search_refs": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32,
                                    _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "knn_timing_enable": (_c.c_int, [_c.c_int32]),
+    "knn_timing_read": (_c.c_int, [_c.c_char_p, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
+    "knn_timing_reset": (_c.c_int, []),
 }
 
 

@@ -6,11 +6,13 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "knn.h"
 #include "knn_internal.h"
@@ -83,6 +85,83 @@ int workspace(hipStream_t stream, size_t bytes, void** out) {
   return KNN_OK;
 }
 
+// ---------------------------------------------------------- kernel timing
+// Optional start/stop events around every launch, on the launch's stream.
+struct TimingRecord {
+  std::string name;
+  hipEvent_t start;
+  hipEvent_t stop;
+};
+
+std::mutex g_tm_mutex;
+bool g_tm_enabled = false;
+std::vector<hipEvent_t> g_tm_pool;
+std::vector<TimingRecord> g_tm_pending;
+std::map<std::string, std::pair<double, int64_t>> g_tm_totals;
+
+hipEvent_t tm_event() {
+  if (!g_tm_pool.empty()) {
+    hipEvent_t e = g_tm_pool.back();
+    g_tm_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// RAII: records a start event now and a stop event when it goes out of scope.
+class TimedLaunch {
+ public:
+  TimedLaunch(const char* name, hipStream_t s) : stream_(s) {
+    std::lock_guard<std::mutex> lock(g_tm_mutex);
+    if (!g_tm_enabled) return;
+    start_ = tm_event();
+    stop_ = tm_event();
+    if (start_ && stop_ && hipEventRecord(start_, s) == hipSuccess) {
+      name_ = name;
+      active_ = true;
+    }
+  }
+  ~TimedLaunch() {
+    if (!active_) return;
+    std::lock_guard<std::mutex> lock(g_tm_mutex);
+    if (hipEventRecord(stop_, stream_) == hipSuccess) g_tm_pending.push_back({name_, start_, stop_});
+  }
+
+ private:
+  hipStream_t stream_;
+  hipEvent_t start_ = nullptr, stop_ = nullptr;
+  std::string name_;
+  bool active_ = false;
+};
+
+int tm_collect() {
+  for (auto& r : g_tm_pending) {
+    hipError_t e = hipEventSynchronize(r.stop);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.start, r.stop);
+    if (e != hipSuccess) return hip_fail(e, "timing events");
+    auto& t = g_tm_totals[r.name];
+    t.first += ms;
+    t.second += 1;
+    g_tm_pool.push_back(r.start);
+    g_tm_pool.push_back(r.stop);
+  }
+  g_tm_pending.clear();
+  return KNN_OK;
+}
+
+const char* fused_name(int kind) {
+  switch (kind) {
+    case TILE_L2_F32: return "fused_l2_f32";
+    case TILE_L2_BF16: return "fused_l2_bf16";
+    case TILE_L2_F16: return "fused_l2_f16";
+    case TILE_L1_F32: return "fused_l1_f32";
+    default: return "fused_linf_f32";
+  }
+}
+
 // -------------------------------------------------------------- planning
 struct Plan {
   int kind = 0;
@@ -99,8 +178,13 @@ struct Plan {
 
 bool is_half_kind(int kind) { return kind == TILE_L2_BF16 || kind == TILE_L2_F16; }
 
-// padded dimension of the rows a tile kind reads
-int padded_dim(int kind, int d) { return (int)round_up(d, is_half_kind(kind) ? 16 : 8); }
+// padded dimension of the rows a tile kind reads: one MFMA k group (16
+// float32 or 32 16-bit dims), or 8 float32 dims for the vector-ALU kinds
+int padded_dim(int kind, int d) {
+  if (is_half_kind(kind)) return (int)round_up(d, 32);
+  if (kind == TILE_L2_F32) return (int)round_up(d, 16);
+  return (int)round_up(d, 8);
+}
 
 int device_cu_count() {
   static int cus = 0;
@@ -114,6 +198,14 @@ int device_cu_count() {
   return cus;
 }
 
+// Environment overrides of the launch plan, for tuning sweeps: KNN_FUSED_WAVES,
+// KNN_FUSED_CB, KNN_FUSED_CW, KNN_FUSED_P.  A value the plan cannot honour is
+// ignored.
+int env_int(const char* name) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : 0;
+}
+
 int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   Plan p;
   p.kind = kind;
@@ -124,21 +216,27 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   // kinds read query values from memory and have no register limit
   const bool mfma = kind <= TILE_L2_F16;
   const int qmax = !mfma ? (1 << 30) : is_half_kind(kind) ? kMaxQChunk16 : kMaxQChunkF32;
-  const int group = is_half_kind(kind) ? 16 : 8;
+  const int group = is_half_kind(kind) ? 32 : kind == TILE_L2_F32 ? 16 : 8;
+  const int ew = env_int("KNN_FUSED_WAVES"), ecb = env_int("KNN_FUSED_CB"), ecw = env_int("KNN_FUSED_CW");
   bool found = false;
-  for (int waves : {4, 2, 1}) {
+  // prefer 8 waves (two per SIMD), then a buffer with slack for several tiles
+  for (int waves : {8, 4, 2, 1}) {
+    if (ew && waves != ew) continue;
     // a staged chunk must fit the per-thread prefetch registers
-    const int cap = std::min({p.dp, qmax, 8 * 64 * waves * 16 / (kStepRefs * p.es)});
-    const int cw = cap / group * group;
-    if (cw < group) continue;
-    for (int cb : {128, 96, 64}) {
-      if (kc + cb > 64 * kMaxMergePerLane) continue;
-      if (fused_lds_bytes(kind, waves, kc, cb, cw) > (size_t)kLdsBytes) continue;
-      p.waves = waves;
-      p.cb = cb;
-      p.cw = cw;
-      found = true;
-      break;
+    int cw = std::min({p.dp, qmax, kPrefetchVecsHost * 64 * waves * 16 / (kStepRefs * p.es)}) / group * group;
+    if (ecw >= group && ecw % group == 0 && ecw < cw) cw = ecw;
+    for (; cw >= group && !found; cw = (cw / 2) / group * group) {
+      for (int cb : {128, 96, 64, 48, 32}) {
+        if (ecb && cb != ecb) continue;
+        if (kc + cb > 64 * kMaxMergePerLane) continue;
+        if (fused_lds_bytes(kind, waves, kc, cb, cw) > (size_t)kLdsBytes) continue;
+        p.waves = waves;
+        p.cb = cb;
+        p.cw = cw;
+        found = true;
+        break;
+      }
+      if (cw == group) break;
     }
     if (found) break;
   }
@@ -152,6 +250,8 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   const int64_t pmax_keys = kFinalMaxKeys / kc;
   const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
   P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)32, pmax_keys, pmax_len}));
+  const int ep = env_int("KNN_FUSED_P");
+  if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
   p.slice_len = round_up(ceil_div(m, P), kStepRefs);
   p.P = (int)ceil_div(m, p.slice_len);
   *out = p;
@@ -232,7 +332,7 @@ int run_search(const SearchArgs& a) {
   const bool prep_q = l2 || !d_pad_free || ((uintptr_t)a.Q % 16) != 0;
 
   const size_t cbytes = centre_refs ? (size_t)round_up((int64_t)a.d * 4, 256) : 0;
-  const size_t pbytes0 = centre_refs ? (size_t)round_up((int64_t)centre_partials(a.m) * a.d * 4, 256) : 0;
+  const size_t pbytes0 = 0;
   const size_t rbytes = prep_refs ? (size_t)round_up(a.m * plan.dp * plan.es, 256) : 0;
   const size_t hbytes = prep_refs && l2 ? (size_t)round_up(a.m * 4, 256) : 0;
   const size_t qbytes = prep_q ? (size_t)round_up(a.n * plan.dp * plan.es, 256) : 0;
@@ -242,7 +342,6 @@ int run_search(const SearchArgs& a) {
   if (st != KNN_OK) return st;
   unsigned char* w = (unsigned char*)ws;
   float* wcentre = (float*)w;
-  float* wpartial = (float*)(w + cbytes);
   unsigned char* wrows = w + cbytes + pbytes0;
   float* wrhalf = (float*)(wrows + rbytes);
   unsigned char* wq = wrows + rbytes + hbytes;
@@ -252,11 +351,13 @@ int run_search(const SearchArgs& a) {
   int ldr = a.ldr;
   const float* rhalf = a.rhalf;
   if (centre_refs) {
-    HIP_TRY(launch_centre(a.R32, a.m, a.d, a.d, wpartial, wcentre, a.stream), "centre launch");
+    TimedLaunch tl("centre", a.stream);
+    HIP_TRY(launch_centre(a.R32, a.m, a.d, a.d, wcentre, a.stream), "centre launch");
     centre = wcentre;
   }
   if (one_shot) {
     if (prep_refs) {
+      TimedLaunch tl("prep_refs", a.stream);
       HIP_TRY(launch_prep_rows(a.R32, a.m, a.d, a.d, centre, wrows, plan.dp, elem_of_kind(a.kind),
                                l2 ? wrhalf : nullptr, a.stream),
               "reference preparation launch");
@@ -270,6 +371,7 @@ int run_search(const SearchArgs& a) {
   const void* qp = a.Q;
   int ldq = a.d;
   if (prep_q) {
+    TimedLaunch tl("prep_queries", a.stream);
     HIP_TRY(launch_prep_rows(a.Q, a.n, a.d, a.d, l2 ? centre : nullptr, wq, plan.dp, elem_of_kind(a.kind), nullptr,
                              a.stream),
             "query preparation launch");
@@ -295,7 +397,10 @@ int run_search(const SearchArgs& a) {
   fp.kc = plan.kc;
   fp.cb = plan.cb;
   fp.waves = plan.waves;
-  HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");
+  {
+    TimedLaunch tl(fused_name(a.kind), a.stream);
+    HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");
+  }
 
   FinalParams fin;
   fin.part = part;
@@ -320,7 +425,10 @@ int run_search(const SearchArgs& a) {
   fin.kprime = a.kprime;
   fin.k = a.k;
   fin.metric = a.metric;
-  HIP_TRY(launch_finalize(fin, a.stream), "finalize launch");
+  {
+    TimedLaunch tl("finalize", a.stream);
+    HIP_TRY(launch_finalize(fin, a.stream), "finalize launch");
+  }
   return KNN_OK;
 }
 
@@ -406,20 +514,16 @@ int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage, int32
   h->dp32 = padded_dim(TILE_L2_F32, d);
   const int es = storage == KNN_FP32 ? 4 : 2;
   const bool master = storage == KNN_FP32 || keep_fp32_master;
-  float* partial = nullptr;
   hipError_t e = hipGetDevice(&h->device);
   if (e == hipSuccess) e = hipMalloc(&h->rows, (size_t)m * h->dp * es);
   if (e == hipSuccess) e = hipMalloc((void**)&h->rhalf, (size_t)m * 4);
   if (e == hipSuccess && master) e = hipMalloc((void**)&h->master, (size_t)m * h->dp32 * 4);
   if (e == hipSuccess && master) e = hipMalloc((void**)&h->centre, (size_t)d * 4);
-  if (e == hipSuccess && master) e = hipMalloc((void**)&partial, (size_t)centre_partials(m) * d * 4);
   // rows are translated by the centre only when a float32 master keeps the
   // untranslated values for the re-rank
-  if (e == hipSuccess && master) e = launch_centre(R, m, d, d, partial, h->centre, s);
+  if (e == hipSuccess && master) e = launch_centre(R, m, d, d, h->centre, s);
   if (e == hipSuccess) e = launch_prep_rows(R, m, d, d, h->centre, h->rows, h->dp, elem_of_kind(kind), h->rhalf, s);
   if (e == hipSuccess && master) e = launch_prep_rows(R, m, d, d, nullptr, h->master, h->dp32, ELEM_F32, nullptr, s);
-  if (e == hipSuccess && partial) e = hipStreamSynchronize(s);
-  if (partial) (void)hipFree(partial);
   if (e != hipSuccess) {
     int rc = hip_fail(e, "knn_create_refs");
     free_refs(h);
@@ -496,6 +600,30 @@ int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32
   a.idx = idx;
   a.stream = (hipStream_t)stream;
   return run_search(a);
+}
+
+int knn_timing_enable(int32_t enable) {
+  std::lock_guard<std::mutex> lock(g_tm_mutex);
+  g_tm_enabled = enable != 0;
+  return KNN_OK;
+}
+
+int knn_timing_read(const char* name, double* total_ms, int64_t* launches) {
+  if (!name) return fail(KNN_ERR_INVALID, "name is NULL");
+  std::lock_guard<std::mutex> lock(g_tm_mutex);
+  int st = tm_collect();
+  if (st != KNN_OK) return st;
+  auto it = g_tm_totals.find(name);
+  if (total_ms) *total_ms = it == g_tm_totals.end() ? 0.0 : it->second.first;
+  if (launches) *launches = it == g_tm_totals.end() ? 0 : it->second.second;
+  return KNN_OK;
+}
+
+int knn_timing_reset(void) {
+  std::lock_guard<std::mutex> lock(g_tm_mutex);
+  int st = tm_collect();
+  g_tm_totals.clear();
+  return st;
 }
 
 }  // extern "C"

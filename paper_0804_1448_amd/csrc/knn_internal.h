@@ -28,13 +28,16 @@ enum ElemType : int { ELEM_F32 = 0, ELEM_BF16 = 1, ELEM_F16 = 2 };
 
 // Fixed geometry of the fused distance + selection kernel.
 constexpr int kWaveSize = 64;
-constexpr int kQueriesPerWave = 32;   // one MFMA 32x32 output column per query
-constexpr int kSubTiles = 2;          // 32-reference sub-tiles per step
-constexpr int kStepRefs = 32 * kSubTiles;  // references scored per step
+constexpr int kQueriesPerWave = 16;   // one MFMA 16x16 output column per query
+constexpr int kTileRefs = 16;         // references per MFMA tile
+constexpr int kTilesPerStep = 4;
+constexpr int kStepRefs = kTileRefs * kTilesPerStep;  // references scored per step
+constexpr int kMaxWaves = 8;          // waves per fused workgroup
 constexpr int kMaxMergePerLane = 8;   // (list + buffer) <= 64 * 8 keys
-constexpr int kMaxQChunkF32 = 128;    // float32 dims held in registers per chunk
+constexpr int kMaxQChunkF32 = 256;    // float32 dims held in registers per chunk
 constexpr int kMaxQChunk16 = 256;     // 16-bit dims held in registers per chunk
 constexpr int kLdsBytes = 160 * 1024; // LDS per compute unit on gfx950
+constexpr int kPrefetchVecsHost = 8;  // 16-byte prefetch registers per thread (fused kernel)
 
 // Parameters of the fused distance + top-k' selection kernel.
 struct FusedParams {
@@ -85,9 +88,7 @@ constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
 // status of the launch.
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst,
                             int ldd, int elem, float* rhalf, hipStream_t stream);
-int centre_partials(int64_t rows);  // partial sums launch_centre needs (times d floats)
-hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* partial, float* centre,
-                         hipStream_t stream);
+hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* centre, hipStream_t stream);
 size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw);
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);

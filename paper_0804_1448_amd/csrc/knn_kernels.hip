@@ -22,7 +22,7 @@
 
 namespace knn {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
@@ -65,49 +65,26 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 // min(m, kCentreRows) rows.  The distance is invariant under a common
 // translation of queries and references, and scores of translated points
 // lose far less to cancellation in |r|^2 / 2 - q.r when the data sits away
-// from the origin.  Two fixed-order passes keep it deterministic.
-constexpr int kCentreRows = 4096;
-constexpr int kCentreRowsPerBlock = 64;
+// from the origin.  One block per 64 dimensions sums the rows in a fixed
+// order, so the centre is deterministic.
+constexpr int kCentreRows = 256;
 
-__global__ __launch_bounds__(256) void centre_partial_kernel(const float* __restrict__ src, int64_t rows, int d,
-                                                             int lds, float* __restrict__ partial) {
+__global__ __launch_bounds__(256) void centre_kernel(const float* __restrict__ src, int64_t rows, int d, int lds,
+                                                     float* __restrict__ centre) {
   __shared__ float red[4][64];
   const int dl = threadIdx.x & 63, ph = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + dl;
-  const int64_t r0 = (int64_t)blockIdx.y * kCentreRowsPerBlock;
+  const int used = (int)(rows < kCentreRows ? rows : kCentreRows);
   float acc = 0.f;
   if (j < d)
-    for (int i = ph; i < kCentreRowsPerBlock; i += 4)
-      if (r0 + i < rows) acc += src[(r0 + i) * lds + j];
+    for (int i = ph; i < used; i += 4) acc += src[(int64_t)i * lds + j];
   red[ph][dl] = acc;
   __syncthreads();
-  if (ph == 0 && j < d) partial[(int64_t)blockIdx.y * d + j] = ((red[0][dl] + red[1][dl]) + red[2][dl]) + red[3][dl];
+  if (ph == 0 && j < d) centre[j] = (((red[0][dl] + red[1][dl]) + red[2][dl]) + red[3][dl]) / (float)used;
 }
 
-__global__ __launch_bounds__(256) void centre_final_kernel(const float* __restrict__ partial, int nparts, int d,
-                                                           int64_t rows, float* __restrict__ centre) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= d) return;
-  float acc = 0.f;
-  for (int b = 0; b < nparts; ++b) acc += partial[(int64_t)b * d + j];
-  centre[j] = acc / (float)rows;
-}
-
-int centre_partials(int64_t rows) {
-  const int64_t used = rows < kCentreRows ? rows : kCentreRows;
-  return (int)((used + kCentreRowsPerBlock - 1) / kCentreRowsPerBlock);
-}
-
-hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* partial, float* centre,
-                         hipStream_t stream) {
-  const int64_t used = rows < kCentreRows ? rows : kCentreRows;
-  const int nparts = centre_partials(rows);
-  hipLaunchKernelGGL(centre_partial_kernel, dim3((unsigned)((d + 63) / 64), (unsigned)nparts), dim3(256), 0, stream,
-                     src, used, d, lds, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(centre_final_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, stream, partial, nparts, d,
-                     used, centre);
+hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* centre, hipStream_t stream) {
+  hipLaunchKernelGGL(centre_kernel, dim3((unsigned)((d + 63) / 64)), dim3(256), 0, stream, src, rows, d, lds, centre);
   return hipGetLastError();
 }
 
@@ -243,21 +220,22 @@ __device__ __forceinline__ void wave_merge(uint64_t* L, const uint64_t* B, int* 
 
 // ------------------------------------------- fused distance + selection
 //
-// Workgroup = `waves` waves; wave w owns queries q0 + 32w .. q0 + 32w + 31
-// and their selection state; all waves share the staged reference tiles.
-// A step scores 64 references (two 32x32 tiles) against the wave's 32
-// queries.  In the 32x32 MFMA output layout lane l holds column l % 32 (its
-// query) and rows 8*(i/4) + 4*(l/32) + i%4, i = 0..15, of each tile; the
-// vector-ALU kernels use the same lane -> (query, reference) layout so that
-// the selection code is shared.
+// Workgroup = `waves` waves (up to 8, two per SIMD); wave w owns 16 queries
+// q0 + 16w .. q0 + 16w + 15 and their selection state; all waves share the
+// reference tiles staged in LDS.  A step scores 64 references (four 16x16
+// tiles) against the wave's 16 queries.  In the 16x16 MFMA output layout
+// lane l holds column l % 16 (its query) and rows 4*(l/16) + i, i = 0..3, of
+// each tile; the vector-ALU kernels compute the same lane -> (query,
+// reference) layout so that the selection code is shared.
 //
 // Selection per query: a sorted list of the kc best keys so far and a buffer
 // of up to cb unsorted candidates, both in LDS.  A score enters the buffer
 // only if it is <= the list's kc-th score (the threshold, +inf until the
-// list is full); a buffer that could overflow in the next step is merged
-// into the list by the whole wave.
+// list is full).  After each tile (at most 16 new candidates per query) a
+// buffer that could overflow on the next tile is merged into the list by the
+// whole wave, which also tightens the threshold.
 
-constexpr int kPrefetchVecs = 8;  // 16-byte global loads per thread per staged tile
+constexpr int kPrefetchVecs = kPrefetchVecsHost;  // 16-byte global loads per thread per staged chunk
 
 template <int KIND>
 struct TileCfg {
@@ -267,13 +245,13 @@ struct TileCfg {
 };
 
 template <int KIND>
-__global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
+__global__ __launch_bounds__(512) void fused_select_kernel(FusedParams p) {
   using Cfg = TileCfg<KIND>;
   constexpr int ES = Cfg::es;
   extern __shared__ __align__(16) unsigned char smem[];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
+  const int lane = tid & 63, wave = tid >> 6, col = lane & 15, kq = lane >> 4;
   const int nthreads = blockDim.x;
   const int nq = p.waves * kQueriesPerWave;
   const int64_t q0 = (int64_t)blockIdx.x * nq;
@@ -299,13 +277,14 @@ __global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
   }
 
   // ---- query operands in registers (MFMA kinds), one chunk of dims at a
-  // time: lane half h holds the dims 8g+4h..8g+4h+3 (float32, group g of
-  // the chunk) or 16s+8h..16s+8h+7 (16-bit, MFMA s of the chunk); A and B
-  // use the same lane -> k mapping, so every product pairs the same
-  // dimension.  Queries are negated so that the MFMA adds -q.r to the
-  // preloaded |r|^2 / 2.
+  // time.  Lane group kq = l / 16 supplies the k slots of the MFMA; group g
+  // of four float32 MFMAs covers dims 16g .. 16g+15, lane group kq holding
+  // 16g+4kq .. 16g+4kq+3; a 16-bit MFMA s covers 32s .. 32s+31, lane group
+  // kq holding 32s+8kq .. 32s+8kq+7.  The reference tile is read with the
+  // same mapping, so every product pairs the same dimension.  Queries are
+  // negated so that the MFMA adds -q.r to the preloaded |r|^2 / 2.
   float4 qf[16];
-  uint4 qh[16];
+  uint4 qh[8];
   auto load_q = [&](int c) {
     const int cb0 = c * p.cw;
     const int cwc = min(p.cw, p.dp - cb0);
@@ -314,18 +293,18 @@ __global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
 #pragma unroll
       for (int g = 0; g < 16; ++g) {
         qf[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g * 8 < cwc && qrow < p.n) {
-          float4 v = *(const float4*)(qp + g * 8 + 4 * h);
+        if (g * 16 < cwc && qrow < p.n) {
+          const float4 v = *(const float4*)(qp + g * 16 + 4 * kq);
           qf[g] = make_float4(-v.x, -v.y, -v.z, -v.w);
         }
       }
     } else if constexpr (Cfg::mfma) {
       const uint16_t* qp = (const uint16_t*)p.Q + qsafe * (int64_t)p.ldq + cb0;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
+      for (int s = 0; s < 8; ++s) {
         qh[s] = make_uint4(0u, 0u, 0u, 0u);
-        if (s * 16 < cwc && qrow < p.n) {
-          uint4 v = *(const uint4*)(qp + s * 16 + 8 * h);
+        if (s * 32 < cwc && qrow < p.n) {
+          const uint4 v = *(const uint4*)(qp + s * 32 + 8 * kq);
           qh[s] = make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
         }
       }
@@ -376,7 +355,7 @@ __global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
 
   const int nsteps = ntiles * p.nchunk;
   float thr = __builtin_huge_valf();
-  f32x16 acc[kSubTiles];
+  f32x4 acc[kTilesPerStep];
 
   if (nsteps > 0) {
     load_stage(0);
@@ -392,70 +371,66 @@ __global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
 
     if (c == 0) {
 #pragma unroll
-      for (int t = 0; t < kSubTiles; ++t) {
+      for (int t = 0; t < kTilesPerStep; ++t) {
         if constexpr (Cfg::mfma) {
-          const float* nb = nbuf + buf * kStepRefs + t * 32 + 4 * h;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            float4 v = *(const float4*)(nb + 8 * j);
-            acc[t][4 * j + 0] = v.x;
-            acc[t][4 * j + 1] = v.y;
-            acc[t][4 * j + 2] = v.z;
-            acc[t][4 * j + 3] = v.w;
-          }
+          const float4 v = *(const float4*)(nbuf + buf * kStepRefs + t * 16 + 4 * kq);
+          acc[t][0] = v.x;
+          acc[t][1] = v.y;
+          acc[t][2] = v.z;
+          acc[t][3] = v.w;
         } else {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+          for (int i = 0; i < 4; ++i) acc[t][i] = 0.f;
         }
       }
     }
 
-    // ---- distance tile on this chunk
+    // ---- distance tiles on this chunk
     const int cwc = min(p.cw, p.dp - c * p.cw);
     if (p.nchunk > 1) load_q(c);
     if constexpr (Cfg::mfma && !Cfg::half16) {
 #pragma unroll
       for (int g = 0; g < 16; ++g) {
-        if (g * 8 < cwc) {
+        if (g * 16 < cwc) {
 #pragma unroll
-          for (int t = 0; t < kSubTiles; ++t) {
-            const float4 a = *(const float4*)(rt + ((t * 32 + col) * p.rstride + g * 8 + 4 * h) * ES);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, qf[g].x, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, qf[g].y, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, qf[g].z, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, qf[g].w, acc[t], 0, 0, 0);
+          for (int t = 0; t < kTilesPerStep; ++t) {
+            const float4 a = *(const float4*)(rt + ((t * 16 + col) * p.rstride + g * 16 + 4 * kq) * ES);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, qf[g].x, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, qf[g].y, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, qf[g].z, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, qf[g].w, acc[t], 0, 0, 0);
           }
         }
       }
     } else if constexpr (Cfg::mfma) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        if (s * 16 < cwc) {
+      for (int s = 0; s < 8; ++s) {
+        if (s * 32 < cwc) {
 #pragma unroll
-          for (int t = 0; t < kSubTiles; ++t) {
-            const uint4 a = *(const uint4*)(rt + ((t * 32 + col) * p.rstride + s * 16 + 8 * h) * ES);
+          for (int t = 0; t < kTilesPerStep; ++t) {
+            const uint4 a = *(const uint4*)(rt + ((t * 16 + col) * p.rstride + s * 32 + 8 * kq) * ES);
             if constexpr (KIND == TILE_L2_BF16)
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                                __builtin_bit_cast(bf16x8, qh[s]), acc[t], 0, 0, 0);
             else
-              acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
                                                               __builtin_bit_cast(f16x8, qh[s]), acc[t], 0, 0, 0);
           }
         }
       }
     } else {
-      // vector ALU: lane (query col, half h) accumulates its 32 rows over the
-      // chunk's dims, 4 at a time; every lane of a half reads the same
+      // vector ALU: lane (query col, group kq) accumulates its 16 rows over
+      // the chunk's dims; every lane of a 16-lane group reads the same
       // reference row (an LDS broadcast).
       const float* qp = (const float*)p.Q + qsafe * (int64_t)p.ldq + c * p.cw;
+      const unsigned char* rbase = rt + (4 * kq) * p.rstride * ES;
       for (int t4 = 0; t4 < cwc; t4 += 4) {
         const float4 qv = *(const float4*)(qp + t4);
 #pragma unroll
-        for (int t = 0; t < kSubTiles; ++t) {
+        for (int t = 0; t < kTilesPerStep; ++t) {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int row = t * 32 + 8 * (i >> 2) + 4 * h + (i & 3);
-            const float4 rv = *(const float4*)(rt + (row * p.rstride + t4) * ES);
+          for (int i = 0; i < 4; ++i) {
+            const float4 rv = *(const float4*)(rbase + ((t * 16 + i) * p.rstride + t4) * ES);
             const float a0 = fabsf(qv.x - rv.x), a1 = fabsf(qv.y - rv.y);
             const float a2 = fabsf(qv.z - rv.z), a3 = fabsf(qv.w - rv.w);
             if constexpr (KIND == TILE_L1_F32)
@@ -467,51 +442,48 @@ __global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
       }
     }
 
-    // ---- selection once the tile has seen every chunk
+    // ---- selection once the tiles have seen every chunk
     if (c == p.nchunk - 1) {
       const int64_t tb = s0 + (int64_t)tile * kStepRefs;
-      const int rowlim = (int)min((int64_t)kStepRefs, s1 - tb) - 4 * h;  // rows r with r + 4h < rowlim are valid
-      uint32_t mask = 0;
+      const int rowlim = (int)min((int64_t)kStepRefs, s1 - tb) - 4 * kq;  // row 16t+4kq+i valid iff 16t+i < rowlim
       float mn = __builtin_huge_valf();
 #pragma unroll
-      for (int t = 0; t < kSubTiles; ++t)
+      for (int t = 0; t < kTilesPerStep; ++t)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) mn = fminf(mn, acc[t][i]);
-      if (mn <= thr) {
+        for (int i = 0; i < 4; ++i) mn = fminf(mn, acc[t][i]);
+      if (ballot(mn <= thr)) {
 #pragma unroll
-        for (int t = 0; t < kSubTiles; ++t)
+        for (int t = 0; t < kTilesPerStep; ++t) {
+          uint32_t mask = 0;
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int r = t * 32 + 8 * (i >> 2) + (i & 3);
-            if (acc[t][i] <= thr && r < rowlim) mask |= 1u << (t * 16 + i);
-          }
-      }
-      const int cnt = __popc(mask);
-      if (ballot(cnt != 0)) {
-        int base = 0;
-        if (cnt) base = atomicAdd(&counts[ql], cnt);
-        uint64_t* dst = bufs + (size_t)ql * cb + base;
-        const uint32_t rbase = (uint32_t)(tb + 4 * h);
+          for (int i = 0; i < 4; ++i)
+            if (acc[t][i] <= thr && t * 16 + i < rowlim) mask |= 1u << i;
+          const int cnt = __popc(mask);
+          if (!ballot(cnt != 0)) continue;
+          int base = 0;
+          if (cnt) base = atomicAdd(&counts[ql], cnt);
+          uint64_t* dst = bufs + (size_t)ql * cb + base;
+          const uint32_t rref = (uint32_t)(tb + t * 16 + 4 * kq);
 #pragma unroll
-        for (int t = 0; t < kSubTiles; ++t)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            if (mask & (1u << (t * 16 + i))) {
-              *dst = make_key(acc[t][i], rbase + (uint32_t)(t * 32 + 8 * (i >> 2) + (i & 3)));
+          for (int i = 0; i < 4; ++i) {
+            if (mask & (1u << i)) {
+              *dst = make_key(acc[t][i], rref + (uint32_t)i);
               ++dst;
             }
           }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const bool need = counts[ql] > cb - kStepRefs;
-        uint64_t needm = ballot(need && h == 0);
-        while (needm) {
-          const int j = __builtin_ctzll(needm);
-          needm &= needm - 1;
-          const int qs = wave * kQueriesPerWave + j;
-          wave_merge(lists + (size_t)qs * kc, bufs + (size_t)qs * cb, lens + qs, counts + qs, kc, lane);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          uint64_t needm = ballot(kq == 0 && counts[ql] > cb - kTileRefs);
+          if (needm) {
+            while (needm) {
+              const int j = __builtin_ctzll(needm);
+              needm &= needm - 1;
+              const int qs = wave * kQueriesPerWave + j;
+              wave_merge(lists + (size_t)qs * kc, bufs + (size_t)qs * cb, lens + qs, counts + qs, kc, lane);
+            }
+            if (lens[ql] == kc) thr = mono_value((uint32_t)(lists[(size_t)ql * kc + kc - 1] >> 32));
+          }
         }
-        if (lens[ql] == kc) thr = mono_value((uint32_t)(lists[(size_t)ql * kc + kc - 1] >> 32));
       }
     }
 
@@ -521,7 +493,7 @@ __global__ __launch_bounds__(256) void fused_select_kernel(FusedParams p) {
 
   // ---- flush the buffers and write this slice's sorted lists
   {
-    uint64_t needm = ballot(counts[ql] > 0 && h == 0);
+    uint64_t needm = ballot(kq == 0 && counts[ql] > 0);
     while (needm) {
       const int j = __builtin_ctzll(needm);
       needm &= needm - 1;
@@ -558,7 +530,8 @@ static hipError_t launch_fused_t(const FusedParams& p, hipStream_t stream) {
     attr_set = true;
   }
   const size_t lds = fused_lds_bytes(KIND, p.waves, p.kc, p.cb, p.cw);
-  dim3 grid((unsigned)((p.n + p.waves * kQueriesPerWave - 1) / (p.waves * kQueriesPerWave)), (unsigned)p.P);
+  const int nq = p.waves * kQueriesPerWave;
+  dim3 grid((unsigned)((p.n + nq - 1) / nq), (unsigned)p.P);
   dim3 block(p.waves * kWaveSize);
   hipLaunchKernelGGL(fused_select_kernel<KIND>, grid, block, lds, stream, p);
   return hipGetLastError();
