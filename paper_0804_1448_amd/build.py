@@ -9,12 +9,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libknn.so")
-SOURCES = ["knn_kernels.hip", "knn_api.cpp"]
+SOURCES = ["knn_kernels.hip", "knn_fused_f32lo.hip", "knn_fused_f32hi.hip", "knn_fused_half.hip",
+           "knn_fused_valu.hip", "knn_api.cpp"]
 
 # Packed float32 instructions are disabled on purpose: the compiler emits
 # them by itself from ordinary float code, and this library does not use them.
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
@@ -27,20 +28,38 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def _compile(src: str, obj: str):
+    cmd = [hipcc(), *HIPCC_FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True), cmd
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source into ``libknn.so`` (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    errs = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln]
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
-    if verbose and errs:
-        print("\n".join(errs), file=sys.stderr)
-    os.replace(tmp, LIB)
+    """Compile every source (in parallel) and link ``libknn.so``; always recompiles."""
+    import tempfile
+
+    with tempfile.TemporaryDirectory(prefix="knn_build_") as tmpd:
+        jobs = []
+        for s in SOURCES:
+            obj = os.path.join(tmpd, s + ".o")
+            jobs.append((obj, *_compile(os.path.join(CSRC, s), obj)))
+        errs = []
+        for obj, proc, cmd in jobs:
+            out, err = proc.communicate()
+            lines = [ln for ln in err.splitlines() if "packed-fp32-ops" not in ln]
+            if proc.returncode != 0:
+                errs.append(" ".join(cmd) + "\n" + "\n".join(lines))
+            elif verbose and lines:
+                print("\n".join(lines), file=sys.stderr)
+        if errs:
+            raise RuntimeError("hipcc failed:\n" + "\n\n".join(errs))
+        tmp = LIB + ".tmp"
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _, _ in jobs], "-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + res.stderr)
+        os.replace(tmp, LIB)
     return LIB
 
 

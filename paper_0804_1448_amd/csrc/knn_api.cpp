@@ -165,9 +165,10 @@ const char* fused_name(int kind) {
 // -------------------------------------------------------------- planning
 struct Plan {
   int kind = 0;
-  int waves = 4;
+  int waves = 8;
   int cb = 64;
-  int cw = 0;
+  int ng = 1;      // k groups per chunk
+  int group = 16;  // dims per k group
   int nchunk = 1;
   int P = 1;
   int64_t slice_len = 0;
@@ -178,13 +179,12 @@ struct Plan {
 
 bool is_half_kind(int kind) { return kind == TILE_L2_BF16 || kind == TILE_L2_F16; }
 
-// padded dimension of the rows a tile kind reads: one MFMA k group (16
-// float32 or 32 16-bit dims), or 8 float32 dims for the vector-ALU kinds
-int padded_dim(int kind, int d) {
-  if (is_half_kind(kind)) return (int)round_up(d, 32);
-  if (kind == TILE_L2_F32) return (int)round_up(d, 16);
-  return (int)round_up(d, 8);
-}
+// dims per k group of a tile kind: four float32 MFMAs (16 dims), one 16-bit
+// MFMA (32 dims), or 16 dims of the vector-ALU kinds
+int group_dims(int kind) { return is_half_kind(kind) ? 32 : 16; }
+
+// padded dimension of the rows a tile kind reads: a whole number of k groups
+int padded_dim(int kind, int d) { return (int)round_up(d, group_dims(kind)); }
 
 int device_cu_count() {
   static int cus = 0;
@@ -210,40 +210,39 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   Plan p;
   p.kind = kind;
   p.kc = kc;
+  p.group = group_dims(kind);
   p.dp = padded_dim(kind, d);
   p.es = is_half_kind(kind) ? 2 : 4;
-  // dims held in query registers per chunk (MFMA kinds); the vector-ALU
-  // kinds read query values from memory and have no register limit
-  const bool mfma = kind <= TILE_L2_F16;
-  const int qmax = !mfma ? (1 << 30) : is_half_kind(kind) ? kMaxQChunk16 : kMaxQChunkF32;
-  const int group = is_half_kind(kind) ? 32 : kind == TILE_L2_F32 ? 16 : 8;
-  const int ew = env_int("KNN_FUSED_WAVES"), ecb = env_int("KNN_FUSED_CB"), ecw = env_int("KNN_FUSED_CW");
+  const int total = p.dp / p.group;
+  const int gmax = kind == TILE_L2_F32 ? kMaxGroupsF32 : is_half_kind(kind) ? kMaxGroups16 : kMaxGroupsValu;
+  const int ew = env_int("KNN_FUSED_WAVES"), ecb = env_int("KNN_FUSED_CB"), eng = env_int("KNN_FUSED_NG");
   bool found = false;
-  // prefer 8 waves (two per SIMD), then a buffer with slack for several tiles
+  // prefer 8 waves (two per SIMD), then the widest chunk, then the largest
+  // candidate buffer (the buffer must hold one step: cb >= 64)
   for (int waves : {8, 4, 2, 1}) {
     if (ew && waves != ew) continue;
-    // a staged chunk must fit the per-thread prefetch registers
-    int cw = std::min({p.dp, qmax, kPrefetchVecsHost * 64 * waves * 16 / (kStepRefs * p.es)}) / group * group;
-    if (ecw >= group && ecw % group == 0 && ecw < cw) cw = ecw;
-    for (; cw >= group && !found; cw = (cw / 2) / group * group) {
-      for (int cb : {128, 96, 64, 48, 32}) {
+    for (int ng = std::min(total, gmax); ng >= 1 && !found; --ng) {
+      if (eng && ng != eng) continue;
+      // with k' <= 64 a 64-key buffer takes the register merge
+      for (int cb : {128, 96, 64}) {
+        if (kc <= 64 && cb > 64 && !ecb) continue;
         if (ecb && cb != ecb) continue;
         if (kc + cb > 64 * kMaxMergePerLane) continue;
-        if (fused_lds_bytes(kind, waves, kc, cb, cw) > (size_t)kLdsBytes) continue;
+        if (fused_lds_bytes(kind, waves, kc, cb, ng * p.group) > (size_t)kLdsBytes) continue;
         p.waves = waves;
         p.cb = cb;
-        p.cw = cw;
+        p.ng = ng;
         found = true;
         break;
       }
-      if (cw == group) break;
     }
     if (found) break;
   }
   if (!found)
     return fail(KNN_ERR_UNSUPPORTED, "k' = %d candidates per query do not fit the fused kernel's LDS budget", kc);
-  p.nchunk = (int)ceil_div(p.dp, p.cw);
-  const int wg_per_cu = std::max<int>(1, (int)(kLdsBytes / fused_lds_bytes(kind, p.waves, kc, p.cb, p.cw)));
+  p.nchunk = (int)ceil_div(total, p.ng);
+  const size_t lds = fused_lds_bytes(kind, p.waves, kc, p.cb, p.ng * p.group);
+  const int wg_per_cu = std::max<int>(1, (int)(kLdsBytes / lds));
   const int64_t nqb = ceil_div(n, (int64_t)p.waves * kQueriesPerWave);
   const int64_t target = (int64_t)device_cu_count() * wg_per_cu;
   int64_t P = ceil_div(target, nqb);
@@ -390,9 +389,8 @@ int run_search(const SearchArgs& a) {
   fp.ldq = ldq;
   fp.ldr = ldr;
   fp.dp = plan.dp;
-  fp.cw = plan.cw;
+  fp.ng = plan.ng;
   fp.nchunk = plan.nchunk;
-  fp.rstride = plan.cw + 16 / plan.es;
   fp.P = plan.P;
   fp.kc = plan.kc;
   fp.cb = plan.cb;
@@ -511,7 +509,7 @@ int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage, int32
   h->storage = storage;
   const int kind = storage == KNN_BF16 ? TILE_L2_BF16 : storage == KNN_FP16 ? TILE_L2_F16 : TILE_L2_F32;
   h->dp = padded_dim(kind, d);
-  h->dp32 = padded_dim(TILE_L2_F32, d);
+  h->dp32 = padded_dim(TILE_L1_F32, d);
   const int es = storage == KNN_FP32 ? 4 : 2;
   const bool master = storage == KNN_FP32 || keep_fp32_master;
   hipError_t e = hipGetDevice(&h->device);

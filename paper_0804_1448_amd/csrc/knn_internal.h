@@ -34,10 +34,10 @@ constexpr int kTilesPerStep = 4;
 constexpr int kStepRefs = kTileRefs * kTilesPerStep;  // references scored per step
 constexpr int kMaxWaves = 8;          // waves per fused workgroup
 constexpr int kMaxMergePerLane = 8;   // (list + buffer) <= 64 * 8 keys
-constexpr int kMaxQChunkF32 = 256;    // float32 dims held in registers per chunk
-constexpr int kMaxQChunk16 = 256;     // 16-bit dims held in registers per chunk
+constexpr int kMaxGroupsF32 = 16;     // float32 MFMA k groups (16 dims) per chunk
+constexpr int kMaxGroups16 = 8;       // 16-bit MFMA k groups (32 dims) per chunk
+constexpr int kMaxGroupsValu = 8;     // vector-ALU groups (16 dims) per chunk
 constexpr int kLdsBytes = 160 * 1024; // LDS per compute unit on gfx950
-constexpr int kPrefetchVecsHost = 8;  // 16-byte prefetch registers per thread (fused kernel)
 
 // Parameters of the fused distance + top-k' selection kernel.
 struct FusedParams {
@@ -50,10 +50,9 @@ struct FusedParams {
   int64_t slice_len;    // references per slice (multiple of kStepRefs)
   int ldq;              // row stride of Q, elements
   int ldr;              // row stride of R, elements
-  int dp;               // padded dimension (multiple of the MFMA k group)
-  int cw;               // dimensions per chunk (the last chunk may be shorter)
-  int nchunk;           // ceil(dp / cw)
-  int rstride;          // LDS row stride of a staged reference tile, elements
+  int dp;               // padded dimension (multiple of the tile kind's k group)
+  int ng;               // k groups per chunk (the kernel's compile-time chunk width)
+  int nchunk;           // ceil(dp / chunk width); the last chunk may be shorter
   int P;                // number of slices
   int kc;               // list capacity = k'
   int cb;               // candidate buffer capacity per query
@@ -91,6 +90,10 @@ hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, cons
 hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* centre, hipStream_t stream);
 size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw);
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream);
+hipError_t launch_fused_f32lo(int ng, const FusedParams& p, hipStream_t stream);
+hipError_t launch_fused_f32hi(int ng, const FusedParams& p, hipStream_t stream);
+hipError_t launch_fused_half(int kind, int ng, const FusedParams& p, hipStream_t stream);
+hipError_t launch_fused_valu(int kind, int ng, const FusedParams& p, hipStream_t stream);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 
 }  // namespace knn

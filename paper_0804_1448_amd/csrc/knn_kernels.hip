@@ -18,47 +18,9 @@
 // into the accumulator.  Manhattan and infinity-norm distances are not
 // contractions and run on the vector ALUs in float32.
 
-#include "knn_internal.h"
+#include "knn_fused.h"
 
 namespace knn {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-// ---------------------------------------------------------------- helpers
-
-// float -> monotone unsigned code: a < b as floats (non-NaN) iff code(a) < code(b)
-__device__ __forceinline__ uint32_t mono_code(float f) {
-  uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float mono_value(uint32_t c) {
-  return __uint_as_float((c & 0x80000000u) ? (c & 0x7fffffffu) : ~c);
-}
-
-__device__ __forceinline__ uint64_t make_key(float score, uint32_t ref) {
-  return ((uint64_t)mono_code(score) << 32) | ref;
-}
-
-// round to nearest even; NaN/Inf are outside the contract
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
-  _Float16 h = (_Float16)f;
-  return __builtin_bit_cast(uint16_t, h);
-}
-
-__device__ __forceinline__ float f16_to_f32(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // ------------------------------------------------------- point preparation
 // Centre of a reference set for the Euclidean scores: the mean of its first
@@ -139,411 +101,21 @@ hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, cons
   return hipGetLastError();
 }
 
-// ------------------------------------------------------ wave-private merge
-// One query's sorted list L (len keys) and unsorted candidate buffer B
-// (c keys) are replaced by the first kc keys of their union, sorted.  All
-// keys are distinct (a reference enters a query's buffer at most once per
-// slice).  Each lane places up to NR keys by rank: a list key at position e
-// moves to e + #{b in B: b < key}; a buffer key goes to #{x in L: x < key} +
-// #{b in B: b < key}.
-template <int NR>
-__device__ __forceinline__ void merge_ranked(uint64_t* L, const uint64_t* B, int len, int c, int kc, int lane) {
-  const int T = len + c;
-  uint64_t x[NR];
-  int below[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int e = lane + 64 * r;
-    x[r] = kEmptyKey;
-    below[r] = 0;
-    if (e < T) x[r] = e < len ? L[e] : B[e - len];
-  }
-  int j = 0;
-  for (; j + 4 <= c; j += 4) {
-    const uint64_t b0 = B[j], b1 = B[j + 1], b2 = B[j + 2], b3 = B[j + 3];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      below[r] += (int)(b0 < x[r]) + (int)(b1 < x[r]) + (int)(b2 < x[r]) + (int)(b3 < x[r]);
-  }
-  for (; j < c; ++j) {
-    const uint64_t b = B[j];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) below[r] += (int)(b < x[r]);
-  }
-  int top = 1;
-  while (top * 2 <= len) top *= 2;
-  int rank[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int e = lane + 64 * r;
-    rank[r] = 0x7fffffff;
-    if (e < len) {
-      rank[r] = e + below[r];
-    } else if (e < T) {
-      int pos = 0;  // number of list keys below x[r]
-      for (int st = top; st > 0; st >>= 1)
-        if (pos + st <= len && L[pos + st - 1] < x[r]) pos += st;
-      rank[r] = pos + below[r];
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (rank[r] < kc) L[rank[r]] = x[r];
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ void wave_merge(uint64_t* L, const uint64_t* B, int* lenp, int* cntp, int kc, int lane) {
-  const int len = *lenp, c = *cntp;
-  const int nr = (len + c + 63) >> 6;
-  switch (nr) {
-    case 0: break;
-    case 1: merge_ranked<1>(L, B, len, c, kc, lane); break;
-    case 2: merge_ranked<2>(L, B, len, c, kc, lane); break;
-    case 3: merge_ranked<3>(L, B, len, c, kc, lane); break;
-    case 4: merge_ranked<4>(L, B, len, c, kc, lane); break;
-    case 5: merge_ranked<5>(L, B, len, c, kc, lane); break;
-    case 6: merge_ranked<6>(L, B, len, c, kc, lane); break;
-    case 7: merge_ranked<7>(L, B, len, c, kc, lane); break;
-    default: merge_ranked<8>(L, B, len, c, kc, lane); break;
-  }
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0) {
-    *lenp = min(kc, len + c);
-    *cntp = 0;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // ------------------------------------------- fused distance + selection
-//
-// Workgroup = `waves` waves (up to 8, two per SIMD); wave w owns 16 queries
-// q0 + 16w .. q0 + 16w + 15 and their selection state; all waves share the
-// reference tiles staged in LDS.  A step scores 64 references (four 16x16
-// tiles) against the wave's 16 queries.  In the 16x16 MFMA output layout
-// lane l holds column l % 16 (its query) and rows 4*(l/16) + i, i = 0..3, of
-// each tile; the vector-ALU kernels compute the same lane -> (query,
-// reference) layout so that the selection code is shared.
-//
-// Selection per query: a sorted list of the kc best keys so far and a buffer
-// of up to cb unsorted candidates, both in LDS.  A score enters the buffer
-// only if it is <= the list's kc-th score (the threshold, +inf until the
-// list is full).  After each tile (at most 16 new candidates per query) a
-// buffer that could overflow on the next tile is merged into the list by the
-// whole wave, which also tightens the threshold.
-
-constexpr int kPrefetchVecs = kPrefetchVecsHost;  // 16-byte global loads per thread per staged chunk
-
-template <int KIND>
-struct TileCfg {
-  static constexpr bool mfma = KIND <= TILE_L2_F16;
-  static constexpr bool half16 = KIND == TILE_L2_BF16 || KIND == TILE_L2_F16;
-  static constexpr int es = half16 ? 2 : 4;  // element size in bytes
-};
-
-template <int KIND>
-__global__ __launch_bounds__(512) void fused_select_kernel(FusedParams p) {
-  using Cfg = TileCfg<KIND>;
-  constexpr int ES = Cfg::es;
-  extern __shared__ __align__(16) unsigned char smem[];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, col = lane & 15, kq = lane >> 4;
-  const int nthreads = blockDim.x;
-  const int nq = p.waves * kQueriesPerWave;
-  const int64_t q0 = (int64_t)blockIdx.x * nq;
-  const int ql = wave * kQueriesPerWave + col;
-  const int64_t qrow = q0 + ql;
-  const int64_t qsafe = qrow < p.n ? qrow : p.n - 1;
-  const int64_t s0 = (int64_t)blockIdx.y * p.slice_len;
-  const int64_t s1 = min(p.m, s0 + p.slice_len);
-  const int ntiles = (int)((s1 - s0 + kStepRefs - 1) / kStepRefs);
-  const int kc = p.kc, cb = p.cb;
-
-  uint64_t* lists = (uint64_t*)smem;
-  uint64_t* bufs = lists + (size_t)nq * kc;
-  int* counts = (int*)(bufs + (size_t)nq * cb);
-  int* lens = counts + nq;
-  float* nbuf = (float*)(lens + nq);
-  unsigned char* rbuf = (unsigned char*)(nbuf + 2 * kStepRefs);
-  const int tile_bytes = kStepRefs * p.rstride * ES;
-
-  for (int i = tid; i < nq; i += nthreads) {
-    counts[i] = 0;
-    lens[i] = 0;
-  }
-
-  // ---- query operands in registers (MFMA kinds), one chunk of dims at a
-  // time.  Lane group kq = l / 16 supplies the k slots of the MFMA; group g
-  // of four float32 MFMAs covers dims 16g .. 16g+15, lane group kq holding
-  // 16g+4kq .. 16g+4kq+3; a 16-bit MFMA s covers 32s .. 32s+31, lane group
-  // kq holding 32s+8kq .. 32s+8kq+7.  The reference tile is read with the
-  // same mapping, so every product pairs the same dimension.  Queries are
-  // negated so that the MFMA adds -q.r to the preloaded |r|^2 / 2.
-  float4 qf[16];
-  uint4 qh[8];
-  auto load_q = [&](int c) {
-    const int cb0 = c * p.cw;
-    const int cwc = min(p.cw, p.dp - cb0);
-    if constexpr (Cfg::mfma && !Cfg::half16) {
-      const float* qp = (const float*)p.Q + qsafe * (int64_t)p.ldq + cb0;
-#pragma unroll
-      for (int g = 0; g < 16; ++g) {
-        qf[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g * 16 < cwc && qrow < p.n) {
-          const float4 v = *(const float4*)(qp + g * 16 + 4 * kq);
-          qf[g] = make_float4(-v.x, -v.y, -v.z, -v.w);
-        }
-      }
-    } else if constexpr (Cfg::mfma) {
-      const uint16_t* qp = (const uint16_t*)p.Q + qsafe * (int64_t)p.ldq + cb0;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        qh[s] = make_uint4(0u, 0u, 0u, 0u);
-        if (s * 32 < cwc && qrow < p.n) {
-          const uint4 v = *(const uint4*)(qp + s * 32 + 8 * kq);
-          qh[s] = make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
-        }
-      }
-    }
-  };
-  if (p.nchunk == 1) load_q(0);
-
-  // ---- staging of reference tiles through registers (double-buffered LDS)
-  uint4 pf[kPrefetchVecs];
-  float pfn = 0.f;
-  int pf_vpr = 0;  // 16-byte vectors per staged row of the prefetched chunk
-  auto load_stage = [&](int step) {
-    const int tile = step / p.nchunk, c = step - tile * p.nchunk;
-    const int64_t rb = s0 + (int64_t)tile * kStepRefs;
-    const int vpr = min(p.cw, p.dp - c * p.cw) * ES / 16;
-    const int nvec = kStepRefs * vpr;
-    pf_vpr = vpr;
-    const unsigned char* gR = (const unsigned char*)p.R;
-#pragma unroll
-    for (int r = 0; r < kPrefetchVecs; ++r) {
-      const int e = tid + r * nthreads;
-      pf[r] = make_uint4(0u, 0u, 0u, 0u);
-      if (e < nvec) {
-        const int row = e / vpr, cv = e - row * vpr;
-        const int64_t g = rb + row;
-        if (g < s1) pf[r] = *(const uint4*)(gR + (g * p.ldr + (int64_t)c * p.cw) * ES + cv * 16);
-      }
-    }
-    if constexpr (Cfg::mfma) {
-      if (tid < kStepRefs) pfn = (rb + tid < s1) ? p.rhalf[rb + tid] : 0.f;
-    }
-  };
-  auto store_stage = [&](int buf) {
-    unsigned char* dst = rbuf + buf * tile_bytes;
-    const int vpr = pf_vpr, nvec = kStepRefs * vpr;
-#pragma unroll
-    for (int r = 0; r < kPrefetchVecs; ++r) {
-      const int e = tid + r * nthreads;
-      if (e < nvec) {
-        const int row = e / vpr, cv = e - row * vpr;
-        *(uint4*)(dst + row * p.rstride * ES + cv * 16) = pf[r];
-      }
-    }
-    if constexpr (Cfg::mfma) {
-      if (tid < kStepRefs) nbuf[buf * kStepRefs + tid] = pfn;
-    }
-  };
-
-  const int nsteps = ntiles * p.nchunk;
-  float thr = __builtin_huge_valf();
-  f32x4 acc[kTilesPerStep];
-
-  if (nsteps > 0) {
-    load_stage(0);
-    store_stage(0);
-  }
-  __syncthreads();
-
-  for (int step = 0; step < nsteps; ++step) {
-    const int buf = step & 1;
-    const int tile = step / p.nchunk, c = step - tile * p.nchunk;
-    if (step + 1 < nsteps) load_stage(step + 1);
-    const unsigned char* rt = rbuf + buf * tile_bytes;
-
-    if (c == 0) {
-#pragma unroll
-      for (int t = 0; t < kTilesPerStep; ++t) {
-        if constexpr (Cfg::mfma) {
-          const float4 v = *(const float4*)(nbuf + buf * kStepRefs + t * 16 + 4 * kq);
-          acc[t][0] = v.x;
-          acc[t][1] = v.y;
-          acc[t][2] = v.z;
-          acc[t][3] = v.w;
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) acc[t][i] = 0.f;
-        }
-      }
-    }
-
-    // ---- distance tiles on this chunk
-    const int cwc = min(p.cw, p.dp - c * p.cw);
-    if (p.nchunk > 1) load_q(c);
-    if constexpr (Cfg::mfma && !Cfg::half16) {
-#pragma unroll
-      for (int g = 0; g < 16; ++g) {
-        if (g * 16 < cwc) {
-#pragma unroll
-          for (int t = 0; t < kTilesPerStep; ++t) {
-            const float4 a = *(const float4*)(rt + ((t * 16 + col) * p.rstride + g * 16 + 4 * kq) * ES);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, qf[g].x, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, qf[g].y, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, qf[g].z, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, qf[g].w, acc[t], 0, 0, 0);
-          }
-        }
-      }
-    } else if constexpr (Cfg::mfma) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        if (s * 32 < cwc) {
-#pragma unroll
-          for (int t = 0; t < kTilesPerStep; ++t) {
-            const uint4 a = *(const uint4*)(rt + ((t * 16 + col) * p.rstride + s * 32 + 8 * kq) * ES);
-            if constexpr (KIND == TILE_L2_BF16)
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                               __builtin_bit_cast(bf16x8, qh[s]), acc[t], 0, 0, 0);
-            else
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
-                                                              __builtin_bit_cast(f16x8, qh[s]), acc[t], 0, 0, 0);
-          }
-        }
-      }
-    } else {
-      // vector ALU: lane (query col, group kq) accumulates its 16 rows over
-      // the chunk's dims; every lane of a 16-lane group reads the same
-      // reference row (an LDS broadcast).
-      const float* qp = (const float*)p.Q + qsafe * (int64_t)p.ldq + c * p.cw;
-      const unsigned char* rbase = rt + (4 * kq) * p.rstride * ES;
-      for (int t4 = 0; t4 < cwc; t4 += 4) {
-        const float4 qv = *(const float4*)(qp + t4);
-#pragma unroll
-        for (int t = 0; t < kTilesPerStep; ++t) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float4 rv = *(const float4*)(rbase + ((t * 16 + i) * p.rstride + t4) * ES);
-            const float a0 = fabsf(qv.x - rv.x), a1 = fabsf(qv.y - rv.y);
-            const float a2 = fabsf(qv.z - rv.z), a3 = fabsf(qv.w - rv.w);
-            if constexpr (KIND == TILE_L1_F32)
-              acc[t][i] = (((acc[t][i] + a0) + a1) + a2) + a3;
-            else
-              acc[t][i] = fmaxf(fmaxf(acc[t][i], fmaxf(a0, a1)), fmaxf(a2, a3));
-          }
-        }
-      }
-    }
-
-    // ---- selection once the tiles have seen every chunk
-    if (c == p.nchunk - 1) {
-      const int64_t tb = s0 + (int64_t)tile * kStepRefs;
-      const int rowlim = (int)min((int64_t)kStepRefs, s1 - tb) - 4 * kq;  // row 16t+4kq+i valid iff 16t+i < rowlim
-      float mn = __builtin_huge_valf();
-#pragma unroll
-      for (int t = 0; t < kTilesPerStep; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) mn = fminf(mn, acc[t][i]);
-      if (ballot(mn <= thr)) {
-#pragma unroll
-        for (int t = 0; t < kTilesPerStep; ++t) {
-          uint32_t mask = 0;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (acc[t][i] <= thr && t * 16 + i < rowlim) mask |= 1u << i;
-          const int cnt = __popc(mask);
-          if (!ballot(cnt != 0)) continue;
-          int base = 0;
-          if (cnt) base = atomicAdd(&counts[ql], cnt);
-          uint64_t* dst = bufs + (size_t)ql * cb + base;
-          const uint32_t rref = (uint32_t)(tb + t * 16 + 4 * kq);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (mask & (1u << i)) {
-              *dst = make_key(acc[t][i], rref + (uint32_t)i);
-              ++dst;
-            }
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          uint64_t needm = ballot(kq == 0 && counts[ql] > cb - kTileRefs);
-          if (needm) {
-            while (needm) {
-              const int j = __builtin_ctzll(needm);
-              needm &= needm - 1;
-              const int qs = wave * kQueriesPerWave + j;
-              wave_merge(lists + (size_t)qs * kc, bufs + (size_t)qs * cb, lens + qs, counts + qs, kc, lane);
-            }
-            if (lens[ql] == kc) thr = mono_value((uint32_t)(lists[(size_t)ql * kc + kc - 1] >> 32));
-          }
-        }
-      }
-    }
-
-    if (step + 1 < nsteps) store_stage(buf ^ 1);
-    __syncthreads();
-  }
-
-  // ---- flush the buffers and write this slice's sorted lists
-  {
-    uint64_t needm = ballot(kq == 0 && counts[ql] > 0);
-    while (needm) {
-      const int j = __builtin_ctzll(needm);
-      needm &= needm - 1;
-      const int qs = wave * kQueriesPerWave + j;
-      wave_merge(lists + (size_t)qs * kc, bufs + (size_t)qs * cb, lens + qs, counts + qs, kc, lane);
-    }
-  }
-  const int tot = kQueriesPerWave * kc;
-  for (int e = lane; e < tot; e += 64) {
-    const int j = e / kc, pos = e - j * kc;
-    const int qs = wave * kQueriesPerWave + j;
-    const int64_t qg = q0 + qs;
-    if (qg < p.n) {
-      const uint64_t key = pos < lens[qs] ? lists[(size_t)qs * kc + pos] : kEmptyKey;
-      p.part[(qg * p.P + blockIdx.y) * kc + pos] = key;
-    }
-  }
-}
+// (kernel template in knn_fused.h; instantiations in knn_fused_*.hip)
 
 size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw) {
   const int es = (kind == TILE_L2_BF16 || kind == TILE_L2_F16) ? 2 : 4;
-  const int pad = 16 / es;
-  const size_t nq = (size_t)waves * kQueriesPerWave;
-  return nq * (size_t)(kc + cb) * 8 + nq * 8 + 2 * kStepRefs * 4 + 2 * (size_t)kStepRefs * (cw + pad) * es;
-}
-
-template <int KIND>
-static hipError_t launch_fused_t(const FusedParams& p, hipStream_t stream) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)fused_select_kernel<KIND>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  const size_t lds = fused_lds_bytes(KIND, p.waves, p.kc, p.cb, p.cw);
-  const int nq = p.waves * kQueriesPerWave;
-  dim3 grid((unsigned)((p.n + nq - 1) / nq), (unsigned)p.P);
-  dim3 block(p.waves * kWaveSize);
-  hipLaunchKernelGGL(fused_select_kernel<KIND>, grid, block, lds, stream, p);
-  return hipGetLastError();
+  return fused_lds_size(es, waves, kc, cb, cw);
 }
 
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream) {
   switch (kind) {
-    case TILE_L2_F32: return launch_fused_t<TILE_L2_F32>(p, stream);
-    case TILE_L2_BF16: return launch_fused_t<TILE_L2_BF16>(p, stream);
-    case TILE_L2_F16: return launch_fused_t<TILE_L2_F16>(p, stream);
-    case TILE_L1_F32: return launch_fused_t<TILE_L1_F32>(p, stream);
-    case TILE_LINF_F32: return launch_fused_t<TILE_LINF_F32>(p, stream);
+    case TILE_L2_F32: return p.ng <= 8 ? launch_fused_f32lo(p.ng, p, stream) : launch_fused_f32hi(p.ng, p, stream);
+    case TILE_L2_BF16:
+    case TILE_L2_F16: return launch_fused_half(kind, p.ng, p, stream);
+    case TILE_L1_F32:
+    case TILE_LINF_F32: return launch_fused_valu(kind, p.ng, p, stream);
     default: return hipErrorInvalidValue;
   }
 }
