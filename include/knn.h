@@ -132,6 +132,123 @@ int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32
                     int32_t precision, int32_t s_extra, float* dist, int32_t* idx, void* stream);
 
 /*
+ * Batched search: many independent instances of the Section 2.1 problem
+ * (each a query set against a resident reference set, with its own n, d, k
+ * and metric), scored in a handful of launches.
+ *   knn_problem_t: one instance.  Q [n][d] device float32 (d of the set),
+ *     dist / idx device outputs [n][k].  1 <= k <= m of the set.
+ *   knn_batch_create(probs, count, precision, s_extra, flags, out): checks
+ *     every instance, plans the launches (instances of the same tile kind and
+ *     padded dimension share a launch; each workgroup takes one
+ *     (instance, query block, reference slice) item, items ordered longest
+ *     first), and allocates the batch's device workspace.  `precision` and
+ *     `s_extra` mean what they mean for knn_search_refs; every set must be
+ *     stored in `precision`.  flags: KNN_BATCH_TUNE times the candidate
+ *     launch configurations of each launch group on the first run and keeps
+ *     the fastest (results unaffected).  The problem array is copied; the
+ *     device buffers it points to must stay valid for every run.
+ *   knn_batch_run(batch, use_graph, stream): enqueues the whole batch.  With
+ *     use_graph != 0 the first run captures the launch sequence into a HIP
+ *     graph on `stream` and later runs replay it (the graph holds no memset
+ *     nodes).  Runs of one batch must not overlap.
+ *   knn_batch_destroy(batch): waits for the device and frees the batch.
+ *   knn_search_batched: create + run (no graph) + destroy.
+ * Errors: KNN_ERR_INVALID (bad instance: the message names its index),
+ * KNN_ERR_UNSUPPORTED, KNN_ERR_OOM, KNN_ERR_DEVICE.
+ */
+typedef struct {
+  knn_refs_t refs;
+  const float* Q;
+  int64_t n;
+  int32_t k;
+  int32_t metric;
+  float* dist;
+  int32_t* idx;
+} knn_problem_t;
+
+typedef struct knn_batch_s* knn_batch_t; /* opaque, owned by the library */
+
+enum knn_batch_flags { KNN_BATCH_TUNE = 1 };
+
+int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precision, int32_t s_extra,
+                     int32_t flags, knn_batch_t* out);
+int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream);
+int knn_batch_destroy(knn_batch_t batch);
+int knn_search_batched(const knn_problem_t* probs, int32_t count, int32_t precision, int32_t s_extra,
+                       void* stream);
+
+/*
+ * Serving engine: resident reference sets answer requests that arrive from
+ * host memory while others are on the device (continuous batching).
+ *   knn_server_create(sets, nsets, cfg, out): `sets` are resident sets (all
+ *     stored in cfg->precision); the engine thread owns one device arena of
+ *     cfg->mem_budget bytes (all request memory: queries, outputs, search
+ *     workspace) and cfg->max_batches streams.
+ *   knn_server_submit(srv, set, Q_host, n, k, dist_host, idx_host, ticket):
+ *     queues a Euclidean search of the n x d host queries against set `set`;
+ *     results land in the host arrays dist_host [n][k], idx_host [n][k],
+ *     which must stay valid until the request is done.  Returns
+ *     KNN_ERR_BUSY when cfg->max_queue requests are already waiting (retry
+ *     later) and KNN_ERR_UNSUPPORTED when the request alone exceeds the
+ *     memory budget.
+ *   Scheduling: requests are admitted in arrival order.  The oldest waiting
+ *     request heads the next batch, which also takes later waiting requests
+ *     of the same set and k, up to cfg->max_batch_queries queries, as long
+ *     as the batch's memory fits in the arena; a batch launches as soon as a
+ *     stream is free, so batches of different sets (or successive batches of
+ *     one set) run on the device at the same time.  A request's result does
+ *     not depend on the requests it is batched with.
+ *   knn_server_poll / knn_server_wait: completion and latency (microseconds
+ *     from submit to results in host memory).  A ticket retires once poll
+ *     has reported it done or wait has returned; a request that failed on
+ *     the device reports its status there.
+ *   KNN_SERVER_DRY_RUN (cfg->flags): no device work; `sets` may be NULL and
+ *     every set has cfg->dry_m references of cfg->dry_d dims; a batch
+ *     completes after cfg->dry_us_per_query * queries microseconds and
+ *     writes dist = set index, idx = the launch sequence number of its
+ *     batch (0, 1, ...; low 31 bits).  For scheduler tests and capacity
+ *     planning.
+ *   knn_server_destroy: finishes every queued request, then frees the engine.
+ * Thread safety: submit, poll, wait and stats may be called from any thread.
+ */
+typedef struct knn_server_s* knn_server_t;
+
+enum knn_server_flags { KNN_SERVER_DRY_RUN = 1 };
+
+typedef struct {
+  int64_t mem_budget;        /* device bytes for requests in flight */
+  int32_t max_batches;       /* batches in flight (one stream each) */
+  int32_t max_queue;         /* waiting requests before submit says KNN_ERR_BUSY */
+  int32_t max_batch_queries; /* queries per batch */
+  int32_t precision;         /* enum knn_precision of the sets */
+  int32_t s_extra;           /* as for knn_search_refs (negative: default) */
+  int32_t flags;             /* enum knn_server_flags */
+  int64_t dry_m;             /* dry run: references per set */
+  int32_t dry_d;             /* dry run: dimension */
+  double dry_us_per_query;   /* dry run: simulated device time per query */
+} knn_server_config_t;
+
+typedef struct {
+  int64_t submitted;
+  int64_t completed;
+  int64_t rejected_busy;
+  int64_t batches;
+  int64_t queries;
+  int32_t peak_batches_in_flight;
+  int64_t peak_mem_in_flight;  /* arena bytes */
+  int64_t mem_budget;
+} knn_server_stats_t;
+
+int knn_server_create(const knn_refs_t* sets, int32_t nsets, const knn_server_config_t* cfg,
+                      knn_server_t* out);
+int knn_server_submit(knn_server_t srv, int32_t set, const float* Q_host, int64_t n, int32_t k,
+                      float* dist_host, int32_t* idx_host, uint64_t* ticket);
+int knn_server_poll(knn_server_t srv, uint64_t ticket, int32_t* done, double* latency_us);
+int knn_server_wait(knn_server_t srv, uint64_t ticket, double* latency_us);
+int knn_server_stats(knn_server_t srv, knn_server_stats_t* out);
+int knn_server_destroy(knn_server_t srv);
+
+/*
  * Kernel timing with HIP events (a measurement aid, not part of the method).
  *   knn_timing_enable(1): every later launch of the library records a start
  *     and a stop event on the stream it is launched on; (0) stops recording.

@@ -15,12 +15,14 @@ import ctypes
 
 import torch
 
-from ._lib import METRICS, PRECISIONS, KnnError, check, load
+from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
+                   ServerStats, check, load)
 
-__all__ = ["search", "Refs", "KnnError", "METRICS", "PRECISIONS", "load", "timing"]
+__all__ = ["search", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
+           "timing"]
 
 KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
-           "fused_l1_f32", "fused_linf_f32", "finalize")
+           "fused_l1_f32", "fused_linf_f32", "finalize", "batch_graph")
 
 
 class timing:
@@ -129,6 +131,168 @@ class Refs:
         if self._h is not None:
             check(load().knn_destroy_refs(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batched search (knn_batch_*): many (refs, Q, k, metric) instances in a few launches.
+
+    ``problems`` is a list of ``(refs, Q, k, metric)``; outputs are allocated
+    here and returned by :meth:`results`.  ``run(use_graph=True)`` captures
+    the launch sequence into a HIP graph on its first call and replays it.
+    """
+
+    def __init__(self, problems, precision: str = "fp32", s_extra: int = -1, tune: bool = False):
+        lib = load()
+        self._keep = []
+        self._out = []
+        arr = (Problem * max(1, len(problems)))()
+        for i, (refs, Q, k, metric) in enumerate(problems):
+            Q = _points(Q, "Q")
+            if Q.shape[1] != refs.d:
+                raise ValueError(f"instance {i}: Q has the wrong dimension for its reference set")
+            dist, idx = _outputs(Q.shape[0], k, Q.device, None)
+            self._keep.append((refs, Q))
+            self._out.append((dist, idx))
+            arr[i] = Problem(refs.handle.value, Q.data_ptr(), Q.shape[0], int(k), METRICS[metric],
+                             dist.data_ptr(), idx.data_ptr())
+        h = ctypes.c_void_p()
+        check(lib.knn_batch_create(arr, len(problems), PRECISIONS[precision], int(s_extra), 1 if tune else 0,
+                                   ctypes.byref(h)))
+        self._h = h
+
+    def run(self, use_graph: bool = False, stream=None):
+        if self._h is None:
+            raise ValueError("batch already closed")
+        check(load().knn_batch_run(self._h, int(bool(use_graph)), _stream_ptr(stream)))
+        return self
+
+    def results(self):
+        return list(self._out)
+
+    def close(self):
+        if self._h is not None:
+            check(load().knn_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def search_batched(problems, precision: str = "fp32", s_extra: int = -1, stream=None):
+    """One-shot batched search: returns [(dist, idx)] in the order of ``problems``."""
+    b = Batch(problems, precision, s_extra)
+    b.run(False, stream)
+    out = b.results()
+    (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    b.close()
+    return out
+
+
+class Server:
+    """Serving engine (knn_server_*): Euclidean requests from host memory,
+    continuously batched onto resident reference sets.
+
+    ``sets`` is a list of :class:`Refs` stored in ``precision``.  :meth:`submit` takes a float32 ``(n, d)`` numpy array
+    and returns a ticket; :meth:`wait` returns ``(dist, idx, latency_us)`` as
+    numpy arrays.  ``submit`` raises :class:`KnnError` with status BUSY when
+    ``max_queue`` requests are already waiting.
+    """
+
+    def __init__(self, sets, mem_budget: int, max_batches: int = 4, max_queue: int = 1024,
+                 max_batch_queries: int = 4096, precision: str = "fp32", s_extra: int = -1):
+        import numpy as np
+
+        self._np = np
+        lib = load()
+        self._sets = list(sets)
+        if not self._sets:
+            raise ValueError("at least one reference set is required")
+        self.d = self._sets[0].d
+        cfg = ServerConfig(int(mem_budget), int(max_batches), int(max_queue), int(max_batch_queries),
+                           PRECISIONS[precision], int(s_extra), 0, 0, 0, 0.0)
+        arr = (ctypes.c_void_p * len(self._sets))(*[r.handle.value for r in self._sets])
+        h = ctypes.c_void_p()
+        check(lib.knn_server_create(arr, len(self._sets), ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    @classmethod
+    def dry(cls, nsets: int, m: int, d: int, us_per_query: float, **kw):
+        """A server that does no device work (scheduler tests, capacity planning)."""
+        srv = cls.__new__(cls)
+        import numpy as np
+
+        srv._np = np
+        lib = load()
+        cfg = ServerConfig(int(kw.get("mem_budget", 1 << 30)), int(kw.get("max_batches", 4)),
+                           int(kw.get("max_queue", 1024)), int(kw.get("max_batch_queries", 4096)),
+                           PRECISIONS[kw.get("precision", "fp32")], int(kw.get("s_extra", -1)), KNN_SERVER_DRY_RUN,
+                           int(m), int(d), float(us_per_query))
+        h = ctypes.c_void_p()
+        check(lib.knn_server_create(None, int(nsets), ctypes.byref(cfg), ctypes.byref(h)))
+        srv._h, srv._live, srv._sets, srv.d = h, {}, [], d
+        return srv
+
+    def submit(self, set_index: int, Q, k: int) -> int:
+        np = self._np
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        if Q.ndim != 2 or Q.shape[1] != self.d:
+            raise ValueError(f"Q must be (n, {self.d})")
+        n = Q.shape[0]
+        dist = np.empty((n, k), np.float32)
+        idx = np.empty((n, k), np.int32)
+        t = ctypes.c_uint64()
+        check(load().knn_server_submit(self._h, int(set_index), Q.ctypes.data, n, int(k), dist.ctypes.data,
+                                       idx.ctypes.data, ctypes.byref(t)))
+        self._live[t.value] = (Q, dist, idx)
+        return t.value
+
+    def poll(self, ticket: int):
+        """``None`` while the request runs, else ``(dist, idx, latency_us)``."""
+        done = ctypes.c_int32()
+        lat = ctypes.c_double()
+        st = load().knn_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(lat))
+        if st != 0:
+            self._live.pop(ticket, None)
+            check(st)
+        if not done.value:
+            return None
+        _, dist, idx = self._live.pop(ticket)
+        return dist, idx, lat.value
+
+    def wait(self, ticket: int):
+        lat = ctypes.c_double()
+        st = load().knn_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(lat))
+        entry = self._live.pop(ticket, None)
+        check(st)
+        _, dist, idx = entry
+        return dist, idx, lat.value
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        check(load().knn_server_stats(self._h, ctypes.byref(out)))
+        return {name: getattr(out, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            check(load().knn_server_destroy(self._h))
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

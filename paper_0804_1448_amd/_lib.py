@@ -26,10 +26,50 @@ SIGNATURES = {
                                  _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "knn_search_refs": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32,
                                    _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "knn_batch_create": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32,
+                                    _c.POINTER(_c.c_void_p)]),
+    "knn_batch_run": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p]),
+    "knn_batch_destroy": (_c.c_int, [_c.c_void_p]),
+    "knn_search_batched": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p]),
     "knn_timing_enable": (_c.c_int, [_c.c_int32]),
     "knn_timing_read": (_c.c_int, [_c.c_char_p, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
     "knn_timing_reset": (_c.c_int, []),
+    "knn_server_create": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.POINTER(_c.c_void_p)]),
+    "knn_server_submit": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
+                                     _c.c_void_p, _c.POINTER(_c.c_uint64)]),
+    "knn_server_poll": (_c.c_int, [_c.c_void_p, _c.c_uint64, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double)]),
+    "knn_server_wait": (_c.c_int, [_c.c_void_p, _c.c_uint64, _c.POINTER(_c.c_double)]),
+    "knn_server_stats": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "knn_server_destroy": (_c.c_int, [_c.c_void_p]),
 }
+
+
+class Problem(_c.Structure):
+    """knn_problem_t: one instance of a batched search."""
+
+    _fields_ = [("refs", _c.c_void_p), ("Q", _c.c_void_p), ("n", _c.c_int64), ("k", _c.c_int32),
+                ("metric", _c.c_int32), ("dist", _c.c_void_p), ("idx", _c.c_void_p)]
+
+
+class ServerConfig(_c.Structure):
+    """knn_server_config_t."""
+
+    _fields_ = [("mem_budget", _c.c_int64), ("max_batches", _c.c_int32), ("max_queue", _c.c_int32),
+                ("max_batch_queries", _c.c_int32), ("precision", _c.c_int32), ("s_extra", _c.c_int32),
+                ("flags", _c.c_int32), ("dry_m", _c.c_int64), ("dry_d", _c.c_int32),
+                ("dry_us_per_query", _c.c_double)]
+
+
+class ServerStats(_c.Structure):
+    """knn_server_stats_t."""
+
+    _fields_ = [("submitted", _c.c_int64), ("completed", _c.c_int64), ("rejected_busy", _c.c_int64),
+                ("batches", _c.c_int64), ("queries", _c.c_int64), ("peak_batches_in_flight", _c.c_int32),
+                ("peak_mem_in_flight", _c.c_int64), ("mem_budget", _c.c_int64)]
+
+
+KNN_ERR_BUSY = -5
+KNN_SERVER_DRY_RUN = 1
 
 
 class KnnError(RuntimeError):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libknn.so")
 SOURCES = ["knn_kernels.hip", "knn_fused_f32lo.hip", "knn_fused_f32hi.hip", "knn_fused_half.hip",
-           "knn_fused_valu.hip", "knn_api.cpp"]
+           "knn_fused_valu.hip", "knn_api.cpp", "knn_server.cpp"]
 
 # Packed float32 instructions are disabled on purpose: the compiler emits
 # them by itself from ordinary float code, and this library does not use them.
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
         if errs:
             raise RuntimeError("hipcc failed:\n" + "\n\n".join(errs))
         tmp = LIB + ".tmp"
-        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _, _ in jobs], "-o", tmp]
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *[o for o, _, _ in jobs], "-o", tmp]
         if verbose:
             print(" ".join(link), flush=True)
         res = subprocess.run(link, capture_output=True, text=True)

@@ -9,18 +9,22 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "knn.h"
+#include "knn_host.h"
 #include "knn_internal.h"
 
 using namespace knn;
+using namespace knn::host;
 
 // ------------------------------------------------------------ error state
-namespace {
+namespace knn::host {
 
 thread_local std::string g_last_error;
 
@@ -39,12 +43,6 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(KNN_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
   return fail(KNN_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                 \
-  do {                                      \
-    hipError_t e_ = (expr);                 \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
@@ -262,61 +260,18 @@ int check_ptr(const void* ptr, const char* name) {
   return KNN_OK;
 }
 
-}  // namespace
+}  // namespace knn::host
 
-// ----------------------------------------------------------- handle type
-// A resident reference set.
-//   rows:   the rows the Euclidean tiles read, in the storage precision,
-//           translated by `centre` (when set) and zero-padded to dp.
-//   rhalf:  half the squared norm of each stored row.
-//   master: float32 rows zero-padded to dp32, untranslated: read by the
-//           exact re-rank and by the Manhattan / infinity-norm tiles.  Absent
-//           only for 16-bit storage without a master, where the stored
-//           (untranslated) rows are canonical.
-struct knn_refs_s {
-  int64_t m = 0;
-  int d = 0;
-  int storage = KNN_FP32;
-  int dp = 0;    // padded dimension of `rows`
-  int dp32 = 0;  // padded dimension of `master`
-  void* rows = nullptr;
-  float* rhalf = nullptr;
-  float* centre = nullptr;
-  float* master = nullptr;
-  int device = 0;
-  uint32_t magic = 0x6b6e6e52u;
-};
+namespace knn::host {
 
-namespace {
-
-// One search, as the pipeline sees it.
-struct SearchArgs {
-  const float* Q;        // caller's float32 queries [n][d]
-  int64_t n;
-  int d;
-  int64_t m;
-  const float* R32;      // one-shot form: caller's float32 references [m][d]; NULL for a handle
-  const void* rows;      // handle form: prepared rows for the tile kind
-  int ldr;
-  const float* rhalf;
-  const float* centre;
-  const void* canon;     // canonical rows for the exact re-rank
-  int canon_type;
-  int ld_canon;
-  int k;
-  int kprime;
-  int metric;
-  int kind;
-  float* dist;
-  int32_t* idx;
-  hipStream_t stream;
-};
 
 int elem_of_kind(int kind) {
   return kind == TILE_L2_BF16 ? ELEM_BF16 : kind == TILE_L2_F16 ? ELEM_F16 : ELEM_F32;
 }
 
-int run_search(const SearchArgs& a) {
+// Run one search in the caller's workspace `ws` of `ws_size` bytes.  With
+// ws == nullptr only the needed size is stored in *need.
+int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need) {
   Plan plan;
   int st = make_plan(a.kind, a.n, a.m, a.d, a.kprime, &plan);
   if (st != KNN_OK) return st;
@@ -336,10 +291,11 @@ int run_search(const SearchArgs& a) {
   const size_t hbytes = prep_refs && l2 ? (size_t)round_up(a.m * 4, 256) : 0;
   const size_t qbytes = prep_q ? (size_t)round_up(a.n * plan.dp * plan.es, 256) : 0;
   const size_t kbytes = (size_t)round_up(a.n * plan.P * (int64_t)plan.kc * 8, 256);
-  void* ws = nullptr;
-  st = workspace(a.stream, cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes, &ws);
-  if (st != KNN_OK) return st;
-  unsigned char* w = (unsigned char*)ws;
+  const size_t total = cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes;
+  if (need) *need = total;
+  if (!ws_in) return KNN_OK;
+  if (ws_size < total) return fail(KNN_ERR_INVALID, "workspace of %zu bytes is smaller than the %zu needed", ws_size, total);
+  unsigned char* w = (unsigned char*)ws_in;
   float* wcentre = (float*)w;
   unsigned char* wrows = w + cbytes + pbytes0;
   float* wrhalf = (float*)(wrows + rbytes);
@@ -378,56 +334,79 @@ int run_search(const SearchArgs& a) {
     ldq = plan.dp;
   }
 
-  FusedParams fp;
-  fp.Q = qp;
-  fp.R = rows;
-  fp.rhalf = rhalf;
-  fp.part = part;
-  fp.n = a.n;
-  fp.m = a.m;
-  fp.slice_len = plan.slice_len;
-  fp.ldq = ldq;
-  fp.ldr = ldr;
-  fp.dp = plan.dp;
+  FusedParams fp{};
+  FusedInst& fi = fp.one;
+  fi.Q = qp;
+  fi.R = rows;
+  fi.rhalf = rhalf;
+  fi.part = part;
+  fi.n = a.n;
+  fi.m = a.m;
+  fi.slice_len = plan.slice_len;
+  fi.ldq = ldq;
+  fi.ldr = ldr;
+  fi.dp = plan.dp;
+  fi.nchunk = plan.nchunk;
+  fi.P = plan.P;
+  fi.kc = plan.kc;
+  fp.insts = nullptr;
+  fp.items = nullptr;
+  fp.nitems = 0;
   fp.ng = plan.ng;
-  fp.nchunk = plan.nchunk;
-  fp.P = plan.P;
-  fp.kc = plan.kc;
   fp.cb = plan.cb;
   fp.waves = plan.waves;
+  fp.kc_max = plan.kc;
   {
     TimedLaunch tl(fused_name(a.kind), a.stream);
     HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");
   }
 
-  FinalParams fin;
-  fin.part = part;
-  fin.Q = a.Q;
-  fin.ldq = a.d;
+  FinalParams fin{};
+  FinalInst& f1 = fin.one;
+  f1.part = part;
+  f1.Q = a.Q;
+  f1.ldq = a.d;
   if (one_shot) {
-    fin.Rm = a.R32;
-    fin.rm_type = ELEM_F32;
-    fin.ldr = a.d;
+    f1.Rm = a.R32;
+    f1.rm_type = ELEM_F32;
+    f1.ldr = a.d;
   } else {
-    fin.Rm = a.canon;
-    fin.rm_type = a.canon_type;
-    fin.ldr = a.ld_canon;
+    f1.Rm = a.canon;
+    f1.rm_type = a.canon_type;
+    f1.ldr = a.ld_canon;
   }
-  fin.dist = a.dist;
-  fin.idx = a.idx;
-  fin.n = a.n;
-  fin.m = a.m;
-  fin.d = a.d;
-  fin.P = plan.P;
-  fin.kc = plan.kc;
-  fin.kprime = a.kprime;
-  fin.k = a.k;
-  fin.metric = a.metric;
+  f1.dist = a.dist;
+  f1.idx = a.idx;
+  f1.n = a.n;
+  f1.m = a.m;
+  f1.d = a.d;
+  f1.P = plan.P;
+  f1.kc = plan.kc;
+  f1.kprime = a.kprime;
+  f1.k = a.k;
+  f1.metric = a.metric;
+  fin.insts = nullptr;
+  fin.items = nullptr;
+  fin.nitems = 0;
+  fin.keys_max = plan.P * plan.kc;
+  fin.p_max = plan.P;
+  fin.kprime_max = a.kprime;
   {
     TimedLaunch tl("finalize", a.stream);
     HIP_TRY(launch_finalize(fin, a.stream), "finalize launch");
   }
   return KNN_OK;
+}
+
+// Run one search in the library's per-stream workspace.
+int run_search(const SearchArgs& a) {
+  size_t need = 0;
+  int st = run_search_ws(a, nullptr, 0, &need);
+  if (st != KNN_OK) return st;
+  void* ws = nullptr;
+  st = workspace(a.stream, need, &ws);
+  if (st != KNN_OK) return st;
+  return run_search_ws(a, ws, need, nullptr);
 }
 
 int check_common(int64_t n, int64_t m, int32_t d, int32_t k, int32_t metric) {
@@ -452,6 +431,55 @@ int default_extra(int precision) { return precision == KNN_FP32 ? 8 : 32; }
 
 bool valid_refs(knn_refs_t r) { return r && r->magic == 0x6b6e6e52u; }
 
+int refs_search_args(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32_t metric, int32_t precision,
+                     int32_t s_extra, float* dist, int32_t* idx, hipStream_t stream, SearchArgs* out) {
+  if (!valid_refs(refs)) return fail(KNN_ERR_INVALID, "not a live reference-set handle");
+  int st = check_common(n, refs->m, refs->d, k, metric);
+  if (st != KNN_OK) return st;
+  if (precision < KNN_FP32 || precision > KNN_FP16) return fail(KNN_ERR_INVALID, "unknown precision %d", precision);
+  if (metric == KNN_L2 && precision != refs->storage)
+    return fail(KNN_ERR_UNSUPPORTED, "precision %d needs rows stored in that precision (stored: %d)", precision,
+                refs->storage);
+  if (metric != KNN_L2 && precision != KNN_FP32)
+    return fail(KNN_ERR_UNSUPPORTED, "low-precision tiles support the Euclidean distance only");
+  if (metric != KNN_L2 && !refs->master)
+    return fail(KNN_ERR_UNSUPPORTED, "Manhattan / infinity-norm search needs float32 rows (create with a master)");
+  if ((st = check_ptr(Q, "Q")) || (st = check_ptr(dist, "dist")) || (st = check_ptr(idx, "idx"))) return st;
+  const int extra = s_extra < 0 ? default_extra(precision) : s_extra;
+  SearchArgs& a = *out;
+  a = SearchArgs{};
+  a.Q = Q;
+  a.n = n;
+  a.d = refs->d;
+  a.m = refs->m;
+  a.kind = tile_kind(metric, precision);
+  if (metric == KNN_L2) {
+    a.rows = refs->rows;
+    a.ldr = refs->dp;
+    a.rhalf = refs->rhalf;
+    a.centre = refs->centre;
+  } else {
+    a.rows = refs->master;
+    a.ldr = refs->dp32;
+  }
+  if (refs->master) {
+    a.canon = refs->master;
+    a.canon_type = ELEM_F32;
+    a.ld_canon = refs->dp32;
+  } else {
+    a.canon = refs->rows;
+    a.canon_type = elem_of_kind(a.kind);
+    a.ld_canon = refs->dp;
+  }
+  a.k = k;
+  a.kprime = (int)std::min<int64_t>(refs->m, (int64_t)k + extra);
+  a.metric = metric;
+  a.dist = dist;
+  a.idx = idx;
+  a.stream = stream;
+  return KNN_OK;
+}
+
 void free_refs(knn_refs_s* h) {
   (void)hipFree(h->rows);
   (void)hipFree(h->rhalf);
@@ -459,7 +487,7 @@ void free_refs(knn_refs_s* h) {
   (void)hipFree(h->master);
 }
 
-}  // namespace
+}  // namespace knn::host
 
 extern "C" {
 
@@ -553,50 +581,13 @@ int knn_refs_info(knn_refs_t refs, int64_t* m, int32_t* d, int32_t* storage, int
 
 int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32_t metric, int32_t precision,
                     int32_t s_extra, float* dist, int32_t* idx, void* stream) {
-  if (!valid_refs(refs)) return fail(KNN_ERR_INVALID, "not a live reference-set handle");
-  int st = check_common(n, refs->m, refs->d, k, metric);
+  if (n == 0) {
+    if (!valid_refs(refs)) return fail(KNN_ERR_INVALID, "not a live reference-set handle");
+    return check_common(n, refs->m, refs->d, k, metric);
+  }
+  SearchArgs a;
+  int st = refs_search_args(refs, Q, n, k, metric, precision, s_extra, dist, idx, (hipStream_t)stream, &a);
   if (st != KNN_OK) return st;
-  if (precision < KNN_FP32 || precision > KNN_FP16) return fail(KNN_ERR_INVALID, "unknown precision %d", precision);
-  if (metric == KNN_L2 && precision != refs->storage)
-    return fail(KNN_ERR_UNSUPPORTED, "precision %d needs rows stored in that precision (stored: %d)", precision,
-                refs->storage);
-  if (metric != KNN_L2 && precision != KNN_FP32)
-    return fail(KNN_ERR_UNSUPPORTED, "low-precision tiles support the Euclidean distance only");
-  if (metric != KNN_L2 && !refs->master)
-    return fail(KNN_ERR_UNSUPPORTED, "Manhattan / infinity-norm search needs float32 rows (create with a master)");
-  if (n == 0) return KNN_OK;
-  if ((st = check_ptr(Q, "Q")) || (st = check_ptr(dist, "dist")) || (st = check_ptr(idx, "idx"))) return st;
-  const int extra = s_extra < 0 ? default_extra(precision) : s_extra;
-  SearchArgs a{};
-  a.Q = Q;
-  a.n = n;
-  a.d = refs->d;
-  a.m = refs->m;
-  a.kind = tile_kind(metric, precision);
-  if (metric == KNN_L2) {
-    a.rows = refs->rows;
-    a.ldr = refs->dp;
-    a.rhalf = refs->rhalf;
-    a.centre = refs->centre;
-  } else {
-    a.rows = refs->master;
-    a.ldr = refs->dp32;
-  }
-  if (refs->master) {
-    a.canon = refs->master;
-    a.canon_type = ELEM_F32;
-    a.ld_canon = refs->dp32;
-  } else {
-    a.canon = refs->rows;
-    a.canon_type = elem_of_kind(a.kind);
-    a.ld_canon = refs->dp;
-  }
-  a.k = k;
-  a.kprime = (int)std::min<int64_t>(refs->m, (int64_t)k + extra);
-  a.metric = metric;
-  a.dist = dist;
-  a.idx = idx;
-  a.stream = (hipStream_t)stream;
   return run_search(a);
 }
 
@@ -622,6 +613,553 @@ int knn_timing_reset(void) {
   int st = tm_collect();
   g_tm_totals.clear();
   return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ batched form
+namespace knn::host {
+
+// One instance of a batch, as planned.
+struct BatchInst {
+  knn_problem_t prob;
+  int kind = 0;
+  int dp = 0;
+  int es = 4;
+  int kc = 0;
+  int kprime = 0;
+  int P = 1;
+  int group = 0;
+  int64_t slice_len = 0;
+  size_t q_off = 0;     // prepared queries in the workspace
+  size_t part_off = 0;  // candidate lists in the workspace
+};
+
+// Instances sharing one fused launch: same tile kind, padded dimension and
+// k' class (k' <= 64 takes the register merge).
+struct BatchGroup {
+  int kind = 0;
+  int dp = 0;
+  int kclass = 0;
+  int ng = 1;
+  int nchunk = 1;
+  int waves = 8;
+  int cb = 64;
+  int kc_max = 0;
+  std::vector<int> insts;
+  size_t insts_off = 0;  // FusedInst table in the workspace
+  size_t items_off = 0;  // FusedItem list (sized for the smallest wave count tried)
+  int nitems = 0;
+  bool tuned = false;
+};
+
+// candidate (waves, cb) launch configurations of a group, best first
+std::vector<std::pair<int, int>> group_configs(const BatchGroup& g) {
+  std::vector<std::pair<int, int>> out;
+  const int group = group_dims(g.kind);
+  for (int waves : {8, 4, 2}) {
+    for (int cb : {64, 96, 128}) {
+      if (g.kc_max <= 64 && cb != 64) continue;
+      if (g.kc_max + cb > 64 * kMaxMergePerLane) continue;
+      if (fused_lds_bytes(g.kind, waves, g.kc_max, cb, g.ng * group) > (size_t)kLdsBytes) continue;
+      out.push_back({waves, cb});
+    }
+  }
+  return out;
+}
+
+// tuned configurations of this process (and of a JSON cache file when
+// KNN_TUNE_CACHE names one), keyed by "kind/dp/kclass/size bucket"
+std::mutex g_tune_mutex;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const BatchGroup& g, int64_t pairs) {
+  int bucket = 0;
+  while (pairs > 1 && bucket < 60) {
+    pairs >>= 2;
+    ++bucket;
+  }
+  char buf[96];
+  snprintf(buf, sizeof buf, "k%d/d%d/c%d/s%d", g.kind, g.dp, g.kclass, bucket);
+  return buf;
+}
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("KNN_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[96];
+  int w = 0, cb = 0;
+  // one entry per line: "key waves cb"
+  while (fscanf(f, "%95s %d %d", key, &w, &cb) == 3) g_tune[key] = {w, cb};
+  fclose(f);
+}
+
+void tune_store() {
+  const char* path = getenv("KNN_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_tune) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+  fclose(f);
+}
+
+}  // namespace knn::host
+
+struct knn_batch_s {
+  uint32_t magic = 0x6b6e6e42u;
+  int precision = KNN_FP32;
+  int flags = 0;
+  std::vector<BatchInst> inst;
+  std::vector<BatchGroup> groups;
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  size_t jobs_off = 0;
+  int64_t prep_rows = 0;
+  size_t finsts_off = 0, fitems_off = 0;
+  int nfitems = 0, keys_max = 0, p_max = 1, kprime_max = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace knn::host {
+
+bool valid_batch(knn_batch_t b) { return b && b->magic == 0x6b6e6e42u; }
+
+// items of group g for `waves` waves per workgroup, longest first
+std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, int waves) {
+  struct Cost {
+    int64_t cost;
+    FusedItem it;
+  };
+  std::vector<Cost> all;
+  const int nq = waves * kQueriesPerWave;
+  for (size_t j = 0; j < g.insts.size(); ++j) {
+    const BatchInst& in = b.inst[g.insts[j]];
+    const int64_t qb = ceil_div(in.prob.n, nq);
+    for (int64_t q = 0; q < qb; ++q) {
+      const int64_t rows = std::min<int64_t>(nq, in.prob.n - q * nq);
+      for (int sl = 0; sl < in.P; ++sl) {
+        const int64_t refs = std::min<int64_t>(in.slice_len, in.prob.refs->m - sl * in.slice_len);
+        // a block costs its full width of queries whatever its fill
+        Cost c;
+        c.cost = (int64_t)nq * refs + rows;
+        c.it.inst = (int)j;
+        c.it.qblock = (int)q;
+        c.it.slice = sl;
+        c.it.pad = 0;
+        all.push_back(c);
+      }
+    }
+  }
+  std::stable_sort(all.begin(), all.end(), [](const Cost& x, const Cost& y) { return x.cost > y.cost; });
+  std::vector<FusedItem> items;
+  items.reserve(all.size());
+  for (auto& c : all) items.push_back(c.it);
+  return items;
+}
+
+int upload(void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return KNN_OK;
+  HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(batch descriptors)");
+  return KNN_OK;
+}
+
+// Fill the group's fused-launch parameters for `waves`/`cb`.
+FusedParams group_params(knn_batch_s& b, const BatchGroup& g, int waves, int cb, int nitems) {
+  FusedParams fp{};
+  unsigned char* w = (unsigned char*)b.ws;
+  fp.insts = (const FusedInst*)(w + g.insts_off);
+  fp.items = (const FusedItem*)(w + g.items_off);
+  fp.nitems = nitems;
+  fp.ng = g.ng;
+  fp.cb = cb;
+  fp.waves = waves;
+  fp.kc_max = g.kc_max;
+  return fp;
+}
+
+int batch_set_group_config(knn_batch_s& b, BatchGroup& g, int waves, int cb) {
+  std::vector<FusedItem> items = group_items(b, g, waves);
+  int st = upload((unsigned char*)b.ws + g.items_off, items.data(), items.size() * sizeof(FusedItem));
+  if (st != KNN_OK) return st;
+  g.waves = waves;
+  g.cb = cb;
+  g.nitems = (int)items.size();
+  return KNN_OK;
+}
+
+// Enqueue the whole batch on `s`.
+int batch_enqueue(knn_batch_s& b, hipStream_t s) {
+  unsigned char* w = (unsigned char*)b.ws;
+  {
+    TimedLaunch tl("prep_queries", s);
+    HIP_TRY(launch_prep_batched((const PrepJob*)(w + b.jobs_off), (int)b.inst.size(), b.prep_rows, s),
+            "batched query preparation launch");
+  }
+  for (BatchGroup& g : b.groups) {
+    FusedParams fp = group_params(b, g, g.waves, g.cb, g.nitems);
+    TimedLaunch tl(fused_name(g.kind), s);
+    HIP_TRY(launch_fused(g.kind, fp, s), "batched fused launch");
+  }
+  FinalParams fin{};
+  fin.insts = (const FinalInst*)(w + b.finsts_off);
+  fin.items = (const FinalItem*)(w + b.fitems_off);
+  fin.nitems = b.nfitems;
+  fin.keys_max = b.keys_max;
+  fin.p_max = b.p_max;
+  fin.kprime_max = b.kprime_max;
+  {
+    TimedLaunch tl("finalize", s);
+    HIP_TRY(launch_finalize(fin, s), "batched finalize launch");
+  }
+  return KNN_OK;
+}
+
+// Time each candidate configuration of every untuned group (the fused
+// launch alone, on the batch's own data) and keep the fastest.
+int batch_tune(knn_batch_s& b, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  tune_load();
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  int st = KNN_OK;
+  for (BatchGroup& g : b.groups) {
+    if (g.tuned) continue;
+    int64_t pairs = 0;
+    for (int j : g.insts) pairs += b.inst[j].prob.n * b.inst[j].prob.refs->m;
+    const std::string key = tune_key(g, pairs);
+    auto hit = g_tune.find(key);
+    if (hit != g_tune.end()) {
+      st = batch_set_group_config(b, g, hit->second.first, hit->second.second);
+      if (st != KNN_OK) break;
+      g.tuned = true;
+      continue;
+    }
+    float best = 1e30f;
+    std::pair<int, int> best_cfg{g.waves, g.cb};
+    for (auto cfg : group_configs(g)) {
+      st = batch_set_group_config(b, g, cfg.first, cfg.second);
+      if (st != KNN_OK) break;
+      FusedParams fp = group_params(b, g, g.waves, g.cb, g.nitems);
+      hipError_t e = launch_fused(g.kind, fp, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_fused(g.kind, fp, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "batch tuning");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_cfg = cfg;
+      }
+    }
+    if (st != KNN_OK) break;
+    st = batch_set_group_config(b, g, best_cfg.first, best_cfg.second);
+    if (st != KNN_OK) break;
+    g_tune[key] = best_cfg;
+    g.tuned = true;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == KNN_OK) tune_store();
+  return st;
+}
+
+void free_batch(knn_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ws) (void)hipFree(b->ws);
+}
+
+}  // namespace knn::host
+
+extern "C" {
+
+int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precision, int32_t s_extra, int32_t flags,
+                     knn_batch_t* out) {
+  if (!out) return fail(KNN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (count < 0) return fail(KNN_ERR_INVALID, "count = %d is negative", count);
+  if (count > 0 && !probs) return fail(KNN_ERR_INVALID, "probs is NULL");
+  if (precision < KNN_FP32 || precision > KNN_FP16) return fail(KNN_ERR_INVALID, "unknown precision %d", precision);
+  std::unique_ptr<knn_batch_s> b(new (std::nothrow) knn_batch_s);
+  if (!b) return fail(KNN_ERR_OOM, "host allocation of the batch failed");
+  b->precision = precision;
+  b->flags = flags;
+  const int extra = s_extra < 0 ? default_extra(precision) : s_extra;
+  // ---- check and plan every instance
+  std::map<std::tuple<int, int, int>, int> group_of;
+  for (int i = 0; i < count; ++i) {
+    const knn_problem_t& pr = probs[i];
+    if (!valid_refs(pr.refs)) return fail(KNN_ERR_INVALID, "instance %d: not a live reference-set handle", i);
+    const knn_refs_s* r = pr.refs;
+    int st = check_common(pr.n, r->m, r->d, pr.k, pr.metric);
+    if (st != KNN_OK) return fail(st, "instance %d: %s", i, g_last_error.c_str());
+    if (pr.metric == KNN_L2 && precision != r->storage)
+      return fail(KNN_ERR_UNSUPPORTED, "instance %d: precision %d needs rows stored in that precision", i, precision);
+    if (pr.metric != KNN_L2 && (precision != KNN_FP32 || !r->master))
+      return fail(KNN_ERR_UNSUPPORTED, "instance %d: Manhattan / infinity norm need float32 tiles and rows", i);
+    if (pr.n > 0 && (!pr.Q || !pr.dist || !pr.idx))
+      return fail(KNN_ERR_INVALID, "instance %d: NULL query or output pointer", i);
+    BatchInst in;
+    in.prob = pr;
+    in.kind = tile_kind(pr.metric, precision);
+    in.dp = padded_dim(in.kind, r->d);
+    in.es = is_half_kind(in.kind) ? 2 : 4;
+    in.kprime = (int)std::min<int64_t>(r->m, (int64_t)pr.k + extra);
+    in.kc = in.kprime;
+    const int kclass = in.kc <= 64 ? 0 : 1;
+    auto key = std::make_tuple(in.kind, in.dp, kclass);
+    auto it = group_of.find(key);
+    if (it == group_of.end()) {
+      BatchGroup g;
+      g.kind = in.kind;
+      g.dp = in.dp;
+      g.kclass = kclass;
+      it = group_of.emplace(key, (int)b->groups.size()).first;
+      b->groups.push_back(g);
+    }
+    in.group = it->second;
+    BatchGroup& g = b->groups[in.group];
+    g.kc_max = std::max(g.kc_max, in.kc);
+    if (pr.n > 0) g.insts.push_back((int)b->inst.size());
+    b->inst.push_back(in);
+  }
+  // ---- launch configuration and slicing of each group
+  const int cus = device_cu_count();
+  for (BatchGroup& g : b->groups) {
+    const int group = group_dims(g.kind);
+    const int total = g.dp / group;
+    const int gmax = g.kind == TILE_L2_F32 ? kMaxGroupsF32 : is_half_kind(g.kind) ? kMaxGroups16 : kMaxGroupsValu;
+    bool found = false;
+    for (int ng = std::min(total, gmax); ng >= 1 && !found; --ng) {
+      g.ng = ng;
+      auto cfgs = group_configs(g);
+      if (!cfgs.empty()) {
+        g.waves = cfgs[0].first;
+        g.cb = cfgs[0].second;
+        found = true;
+      }
+    }
+    if (!found)
+      return fail(KNN_ERR_UNSUPPORTED, "k' = %d candidates per query do not fit the fused kernel's LDS budget",
+                  g.kc_max);
+    g.nchunk = (int)ceil_div(total, g.ng);
+    // slice length: about four items per workgroup slot of the whole device
+    const int nq = g.waves * kQueriesPerWave;
+    const size_t lds = fused_lds_bytes(g.kind, g.waves, g.kc_max, g.cb, g.ng * group);
+    const int64_t slots = (int64_t)cus * std::max<int>(1, (int)(kLdsBytes / lds));
+    int64_t blockrefs = 0;
+    for (int j : g.insts) blockrefs += ceil_div(b->inst[j].prob.n, nq) * b->inst[j].prob.refs->m;
+    int64_t slice = round_up(std::max<int64_t>(1, blockrefs / std::max<int64_t>(1, 4 * slots)), kStepRefs);
+    slice = std::max<int64_t>(slice, 16 * kStepRefs);
+    for (int j : g.insts) {
+      BatchInst& in = b->inst[j];
+      const int64_t m = in.prob.refs->m;
+      const int64_t pmax = std::max<int64_t>(1, kFinalMaxKeys / in.kc);
+      const int64_t P = std::min<int64_t>(pmax, ceil_div(m, slice));
+      in.slice_len = round_up(ceil_div(m, P), kStepRefs);
+      in.P = (int)ceil_div(m, in.slice_len);
+    }
+  }
+  // ---- workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (size_t)round_up((int64_t)bytes, 256);
+    return at;
+  };
+  for (BatchInst& in : b->inst) {
+    in.q_off = take((size_t)in.prob.n * in.dp * in.es);
+    in.part_off = take((size_t)in.prob.n * in.P * in.kc * 8);
+  }
+  for (BatchGroup& g : b->groups) {
+    g.insts_off = take(g.insts.size() * sizeof(FusedInst));
+    size_t most = 0;
+    for (int waves : {8, 4, 2}) most = std::max(most, group_items(*b, g, waves).size());
+    g.items_off = take(most * sizeof(FusedItem));
+  }
+  b->jobs_off = take(b->inst.size() * sizeof(PrepJob));
+  b->finsts_off = take(b->inst.size() * sizeof(FinalInst));
+  int64_t nf = 0;
+  for (BatchInst& in : b->inst) nf += ceil_div(in.prob.n, kFinalWaves);
+  b->fitems_off = take((size_t)nf * sizeof(FinalItem));
+  b->ws_size = std::max<size_t>(off, 256);
+  hipError_t e = hipMalloc(&b->ws, b->ws_size);
+  if (e != hipSuccess) {
+    b->ws = nullptr;
+    return hip_fail(e, "hipMalloc(batch workspace)");
+  }
+  std::unique_ptr<knn_batch_s, void (*)(knn_batch_s*)> guard(b.get(), [](knn_batch_s* p) { free_batch(p); });
+  unsigned char* w = (unsigned char*)b->ws;
+  // ---- descriptors: query preparation, fused instances and items, finalize
+  std::vector<PrepJob> jobs;
+  std::vector<FinalInst> finsts;
+  std::vector<FinalItem> fitems;
+  int64_t row0 = 0;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    const BatchInst& in = b->inst[i];
+    const knn_refs_s* r = in.prob.refs;
+    const bool l2 = in.kind <= TILE_L2_F16;
+    PrepJob jb{};
+    jb.src = in.prob.Q;
+    jb.dst = w + in.q_off;
+    jb.centre = l2 ? r->centre : nullptr;
+    jb.rhalf = nullptr;
+    jb.rows = in.prob.n;
+    jb.row0 = row0;
+    jb.d = r->d;
+    jb.lds = r->d;
+    jb.ldd = in.dp;
+    jb.elem = elem_of_kind(in.kind);
+    jobs.push_back(jb);
+    row0 += in.prob.n;
+    FinalInst fi{};
+    fi.part = (const uint64_t*)(w + in.part_off);
+    fi.Q = in.prob.Q;
+    fi.ldq = r->d;
+    if (r->master) {
+      fi.Rm = r->master;
+      fi.rm_type = ELEM_F32;
+      fi.ldr = r->dp32;
+    } else {
+      fi.Rm = r->rows;
+      fi.rm_type = elem_of_kind(in.kind);
+      fi.ldr = r->dp;
+    }
+    fi.dist = in.prob.dist;
+    fi.idx = in.prob.idx;
+    fi.n = in.prob.n;
+    fi.m = r->m;
+    fi.d = r->d;
+    fi.P = in.P;
+    fi.kc = in.kc;
+    fi.kprime = in.kprime;
+    fi.k = in.prob.k;
+    fi.metric = in.prob.metric;
+    finsts.push_back(fi);
+    for (int64_t q = 0; q < in.prob.n; q += kFinalWaves) fitems.push_back({(int)i, (int)q});
+    b->keys_max = std::max(b->keys_max, in.P * in.kc);
+    b->p_max = std::max(b->p_max, in.P);
+    b->kprime_max = std::max(b->kprime_max, in.kprime);
+  }
+  b->prep_rows = row0;
+  b->nfitems = (int)fitems.size();
+  int st = upload(w + b->jobs_off, jobs.data(), jobs.size() * sizeof(PrepJob));
+  if (st == KNN_OK) st = upload(w + b->finsts_off, finsts.data(), finsts.size() * sizeof(FinalInst));
+  if (st == KNN_OK) st = upload(w + b->fitems_off, fitems.data(), fitems.size() * sizeof(FinalItem));
+  for (BatchGroup& g : b->groups) {
+    if (st != KNN_OK) break;
+    std::vector<FusedInst> fis;
+    for (int j : g.insts) {
+      const BatchInst& in = b->inst[j];
+      const knn_refs_s* r = in.prob.refs;
+      FusedInst fi{};
+      fi.Q = w + in.q_off;
+      if (in.kind <= TILE_L2_F16) {
+        fi.R = r->rows;
+        fi.ldr = r->dp;
+        fi.rhalf = r->rhalf;
+      } else {
+        fi.R = r->master;
+        fi.ldr = r->dp32;
+        fi.rhalf = nullptr;
+      }
+      fi.part = (uint64_t*)(w + in.part_off);
+      fi.n = in.prob.n;
+      fi.m = r->m;
+      fi.slice_len = in.slice_len;
+      fi.ldq = in.dp;
+      fi.dp = in.dp;
+      fi.nchunk = g.nchunk;
+      fi.P = in.P;
+      fi.kc = in.kc;
+      fis.push_back(fi);
+    }
+    st = upload(w + g.insts_off, fis.data(), fis.size() * sizeof(FusedInst));
+    if (st == KNN_OK) st = batch_set_group_config(*b, g, g.waves, g.cb);
+  }
+  if (st != KNN_OK) return st;
+  guard.release();
+  *out = b.release();
+  return KNN_OK;
+}
+
+int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream) {
+  if (!valid_batch(batch)) return fail(KNN_ERR_INVALID, "not a live batch handle");
+  hipStream_t s = (hipStream_t)stream;
+  if ((batch->flags & KNN_BATCH_TUNE)) {
+    int st = batch_tune(*batch, s);
+    if (st != KNN_OK) return st;
+  }
+  if (!use_graph) return batch_enqueue(*batch, s);
+  if (!batch->exec) {
+    // first graph run: run eagerly (this also sets the kernels' launch
+    // attributes), then capture the same sequence for later replays
+    int st = batch_enqueue(*batch, s);
+    if (st != KNN_OK) return st;
+    bool timing;
+    {
+      std::lock_guard<std::mutex> lock(g_tm_mutex);
+      timing = g_tm_enabled;
+      g_tm_enabled = false;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    st = batch_enqueue(*batch, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    {
+      std::lock_guard<std::mutex> lock(g_tm_mutex);
+      g_tm_enabled = timing;
+    }
+    if (st != KNN_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    batch->graph = graph;
+    batch->exec = exec;
+    return KNN_OK;
+  }
+  TimedLaunch tl("batch_graph", s);
+  HIP_TRY(hipGraphLaunch(batch->exec, s), "hipGraphLaunch");
+  return KNN_OK;
+}
+
+int knn_batch_destroy(knn_batch_t batch) {
+  if (!valid_batch(batch)) return fail(KNN_ERR_INVALID, "not a live batch handle");
+  batch->magic = 0;
+  hipError_t e = hipDeviceSynchronize();
+  free_batch(batch);
+  delete batch;
+  if (e != hipSuccess) return hip_fail(e, "knn_batch_destroy");
+  return KNN_OK;
+}
+
+int knn_search_batched(const knn_problem_t* probs, int32_t count, int32_t precision, int32_t s_extra,
+                       void* stream) {
+  knn_batch_t b = nullptr;
+  int st = knn_batch_create(probs, count, precision, s_extra, 0, &b);
+  if (st != KNN_OK) return st;
+  st = knn_batch_run(b, 0, stream);
+  const int st2 = knn_batch_destroy(b);
+  return st != KNN_OK ? st : st2;
 }
 
 }  // extern "C"

@@ -69,14 +69,25 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
   const int lane = tid & 63, wave = tid >> 6, col = lane & 15, kq = lane >> 4;
   const int W = p.waves;
   const int nq = W * kQueriesPerWave;
-  const int64_t q0 = (int64_t)blockIdx.x * nq;
+  // this workgroup's instance, query block and reference slice
+  int qblock = blockIdx.x, slice = blockIdx.y;
+  FusedInst in;
+  if (p.items) {
+    const FusedItem it = p.items[blockIdx.x];
+    in = p.insts[it.inst];
+    qblock = it.qblock;
+    slice = it.slice;
+  } else {
+    in = p.one;
+  }
+  const int64_t q0 = (int64_t)qblock * nq;
   const int ql = wave * kQueriesPerWave + col;
   const int64_t qrow = q0 + ql;
-  const int64_t qsafe = qrow < p.n ? qrow : p.n - 1;
-  const int64_t s0 = (int64_t)blockIdx.y * p.slice_len;
-  const int64_t s1 = min(p.m, s0 + p.slice_len);
+  const int64_t qsafe = qrow < in.n ? qrow : in.n - 1;
+  const int64_t s0 = (int64_t)slice * in.slice_len;
+  const int64_t s1 = min(in.m, s0 + in.slice_len);
   const int ntiles = (int)((s1 - s0 + kStepRefs - 1) / kStepRefs);
-  const int kc = p.kc, cb = p.cb;
+  const int kc = in.kc, cb = p.cb;
 
   // per-query buffer: 4 segments of `sub` keys, each padded by one key and
   // the query's block by one more, so that lanes appending in parallel
@@ -87,8 +98,12 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
   uint64_t* lists = (uint64_t*)smem;
   uint64_t* bufs = lists + (size_t)nq * kc;
   int* lens = (int*)(bufs + (size_t)nq * q_stride);
-  float* nbuf = (float*)(lens + nq);
-  unsigned char* rbuf = (unsigned char*)(nbuf + 2 * kStepRefs);
+  // The double-buffered tiles (and norms) are separate static arrays and the
+  // step loop below is unrolled by two, so that every read of one buffer is
+  // provably disjoint from the asynchronous copy into the other: the copy's
+  // completion is then awaited only at the end of the step.
+  __shared__ __align__(16) unsigned char tile0[TILE_BYTES], tile1[TILE_BYTES];
+  __shared__ __align__(16) float norm0[kStepRefs], norm1[kStepRefs];
 
   for (int i = tid; i < nq; i += blockDim.x) lens[i] = 0;
 
@@ -102,10 +117,10 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
   // vector-ALU kinds read their query values from memory, one group ahead.)
   float4 qf[NG];
   uint4 qh[NG];
-  auto load_q = [&](int c) {
-    const int ngv = min(NG, (p.dp - c * CW) / G);
+  auto load_q = [&](int c) __attribute__((always_inline)) {
+    const int ngv = min(NG, (in.dp - c * CW) / G);
     if constexpr (Cfg::mfma && !Cfg::half16) {
-      const float* qp = (const float*)p.Q + qsafe * (int64_t)p.ldq + c * CW;
+      const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq + c * CW;
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         qf[g] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -115,7 +130,7 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
         }
       }
     } else if constexpr (Cfg::mfma) {
-      const uint16_t* qp = (const uint16_t*)p.Q + qsafe * (int64_t)p.ldq + c * CW;
+      const uint16_t* qp = (const uint16_t*)in.Q + qsafe * (int64_t)in.ldq + c * CW;
 #pragma unroll
       for (int s = 0; s < NG; ++s) {
         qh[s] = make_uint4(0u, 0u, 0u, 0u);
@@ -126,20 +141,19 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
       }
     }
   };
-  if (p.nchunk == 1) load_q(0);
+  if (in.nchunk == 1) load_q(0);
 
   // ---- staging: slot (row, logical chunk j) of a tile lives at
   // row * VPR + (j ^ (row & SWZ)); a wave instruction fills 64 consecutive
   // slots.  Rows past the slice end and chunks past the row's valid dims
   // load clamped (valid) addresses; their scores are masked, and their
   // products meet zero query operands.
-  auto stage = [&](int stile, int sc, int buf) {
+  auto stage = [&](int stile, int sc, unsigned char* dst, float* ndst) __attribute__((always_inline)) {
     const int64_t rb = s0 + (int64_t)stile * kStepRefs;
-    const int vvalid = min(VPR, (p.dp - sc * CW) * ES / 16);
+    const int vvalid = min(VPR, (in.dp - sc * CW) * ES / 16);
     const int rlast = (int)min((int64_t)kStepRefs, s1 - rb) - 1;  // last valid row of the tile
-    unsigned char* dst = rbuf + buf * TILE_BYTES;
-    const unsigned char* gR = (const unsigned char*)p.R + (rb * p.ldr + (int64_t)sc * CW) * ES;
-    const int rowbytes = p.ldr * ES;
+    const unsigned char* gR = (const unsigned char*)in.R + (rb * in.ldr + (int64_t)sc * CW) * ES;
+    const int rowbytes = in.ldr * ES;
     for (int i = wave; i < VPR; i += W) {
       const int s = 64 * i + lane;
       const int row = s / VPR, jp = s - row * VPR;
@@ -149,12 +163,11 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
     }
     if constexpr (Cfg::mfma) {
       if (wave == W - 1)
-        __builtin_amdgcn_global_load_lds(p.rhalf + rb + min(lane, rlast), (lds_void*)(nbuf + buf * kStepRefs), 4, 0,
-                                         0);
+        __builtin_amdgcn_global_load_lds(in.rhalf + rb + min(lane, rlast), (lds_void*)ndst, 4, 0, 0);
     }
   };
 
-  const int nsteps = ntiles * p.nchunk;
+  const int nsteps = ntiles * in.nchunk;
   float thr = __builtin_huge_valf();
   int lcnt = 0;  // keys in this lane's buffer segment
   uint64_t* myseg = bufs + (size_t)ql * q_stride + kq * seg_stride;
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
   // merge the buffers of the wave's queries flagged in `qmask` (bit j =
   // query j of the wave) into their lists, then refresh this lane's count
   // and threshold if its query was merged
-  auto merge_queries = [&](uint32_t qmask) {
+  auto merge_queries = [&](uint32_t qmask) __attribute__((always_inline)) {
     wave_sync();
     uint32_t todo = qmask;
     while (todo) {
@@ -185,28 +198,29 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
       if (lens[ql] == kc) thr = mono_value((uint32_t)(lists[(size_t)ql * kc + kc - 1] >> 32));
     }
   };
-  auto query_bits = [](uint64_t lanes) {  // lanes col + 16k -> bit col
+  auto query_bits = [](uint64_t lanes) __attribute__((always_inline)) {  // lanes col + 16k -> bit col
     return (uint32_t)((lanes | (lanes >> 16) | (lanes >> 32) | (lanes >> 48)) & 0xffffu);
   };
 
-  if (nsteps > 0) stage(0, 0, 0);
+  if (nsteps > 0) stage(0, 0, tile0, norm0);
   wait_vmem();
   __syncthreads();
 
   int tile = 0, c = 0;
-  for (int step = 0; step < nsteps; ++step) {
-    const int buf = step & 1;
+  // one step: stage the next chunk into (wt, nwr), score the chunk held in
+  // (rt, nrd), select if the tile is complete, then wait for the copy and
+  // synchronize
+  auto run_step = [&](int step, const unsigned char* rt, const float* nrd, unsigned char* wt, float* nwr) __attribute__((always_inline)) {
     if (step + 1 < nsteps) {
-      const bool wrap = c + 1 == p.nchunk;
-      stage(wrap ? tile + 1 : tile, wrap ? 0 : c + 1, buf ^ 1);
+      const bool wrap = c + 1 == in.nchunk;
+      stage(wrap ? tile + 1 : tile, wrap ? 0 : c + 1, wt, nwr);
     }
-    const unsigned char* rt = rbuf + buf * TILE_BYTES;
 
     if (c == 0) {
 #pragma unroll
       for (int t = 0; t < kTilesPerStep; ++t) {
         if constexpr (Cfg::mfma) {
-          const float4 v = *(const float4*)(nbuf + buf * kStepRefs + t * 16 + 4 * kq);
+          const float4 v = *(const float4*)(nrd + t * 16 + 4 * kq);
           acc[t][0] = v.x;
           acc[t][1] = v.y;
           acc[t][2] = v.z;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
     }
 
     // ---- distance tiles on this chunk
-    if (p.nchunk > 1) load_q(c);
+    if (in.nchunk > 1) load_q(c);
     if constexpr (Cfg::mfma) {
       const int sw = col & SWZ;  // swizzle of rows 16t + col
 #pragma unroll
@@ -248,8 +262,8 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
       // vector ALU: lane (query col, group kq) accumulates rows 16t+4kq+i over
       // the chunk's dims, 16 at a time; the 16 lanes of a group read the same
       // reference row (an LDS broadcast).  Row 16t+4kq+i has swizzle i & 3.
-      const int ngv = min(NG, (p.dp - c * CW) / G);
-      const float* qp = (const float*)p.Q + qsafe * (int64_t)p.ldq + c * CW;
+      const int ngv = min(NG, (in.dp - c * CW) / G);
+      const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq + c * CW;
       float4 qn[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) qn[j] = *(const float4*)(qp + 4 * j);
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
     }
 
     // ---- selection once the tiles have seen every chunk
-    if (c == p.nchunk - 1) {
+    if (c == in.nchunk - 1) {
       const int64_t tb = s0 + (int64_t)tile * kStepRefs;
       if (tb + kStepRefs > s1) {  // last, partial step of the slice
         const int rowlim = (int)(s1 - tb);
@@ -322,10 +336,14 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
 
     wait_vmem();
     __syncthreads();
-    if (++c == p.nchunk) {
+    if (++c == in.nchunk) {
       c = 0;
       ++tile;
     }
+  };
+  for (int step = 0; step < nsteps; step += 2) {
+    run_step(step, tile0, norm0, tile1, norm1);
+    if (step + 1 < nsteps) run_step(step + 1, tile1, norm1, tile0, norm0);
   }
 
   // ---- write this slice's sorted lists
@@ -334,31 +352,38 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
     const int j = e / kc, pos = e - j * kc;
     const int qs = wave * kQueriesPerWave + j;
     const int64_t qg = q0 + qs;
-    if (qg < p.n) {
+    if (qg < in.n) {
       const uint64_t key = pos < lens[qs] ? lists[(size_t)qs * kc + pos] : kEmptyKey;
-      p.part[(qg * p.P + blockIdx.y) * kc + pos] = key;
+      in.part[(qg * in.P + slice) * kc + pos] = key;
     }
   }
 }
 
-// LDS bytes of one fused workgroup.
+// LDS bytes of one fused workgroup: the dynamic selection state plus the
+// static tile and norm buffers.
+__host__ __device__ constexpr size_t fused_dyn_lds(int waves, int kc, int cb) {
+  return (size_t)waves * kQueriesPerWave * ((size_t)(kc + cb + 5) * 8 + 4);
+}
 __host__ __device__ constexpr size_t fused_lds_size(int es, int waves, int kc, int cb, int cw) {
-  return (size_t)waves * kQueriesPerWave * ((size_t)(kc + cb + 5) * 8 + 4) + 2 * kStepRefs * 4 +
-         2 * (size_t)kStepRefs * cw * es;
+  return fused_dyn_lds(waves, kc, cb) + 2 * kStepRefs * 4 + 2 * (size_t)kStepRefs * cw * es;
 }
 
 template <int KIND, int NG>
 hipError_t launch_fused_one(const FusedParams& p, hipStream_t stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)fused_kernel<KIND, NG>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, (const void*)fused_kernel<KIND, NG>);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)fused_kernel<KIND, NG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes - (int)fa.sharedSizeBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const size_t lds = fused_lds_size(TileCfg<KIND>::es, p.waves, p.kc, p.cb, NG * TileCfg<KIND>::group);
+  const size_t lds = fused_dyn_lds(p.waves, p.kc_max, p.cb);
   const int nq = p.waves * kQueriesPerWave;
-  dim3 grid((unsigned)((p.n + nq - 1) / nq), (unsigned)p.P);
+  if (p.items && p.nitems <= 0) return hipSuccess;
+  dim3 grid = p.items ? dim3((unsigned)p.nitems) : dim3((unsigned)((p.one.n + nq - 1) / nq), (unsigned)p.one.P);
   dim3 block(p.waves * kWaveSize);
   hipLaunchKernelGGL((fused_kernel<KIND, NG>), grid, block, lds, stream, p);
   return hipGetLastError();

@@ -1,0 +1,78 @@
+// knn_host.h -- host-side internals shared by the C ABI (knn_api.cpp) and
+// the serving engine (knn_server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "knn.h"
+#include "knn_internal.h"
+
+// ----------------------------------------------------------- handle type
+// A resident reference set.
+//   rows:   the rows the Euclidean tiles read, in the storage precision,
+//           translated by `centre` (when set) and zero-padded to dp.
+//   rhalf:  half the squared norm of each stored row.
+//   master: float32 rows zero-padded to dp32, untranslated: read by the
+//           exact re-rank and by the Manhattan / infinity-norm tiles.  Absent
+//           only for 16-bit storage without a master, where the stored
+//           (untranslated) rows are canonical.
+struct knn_refs_s {
+  int64_t m = 0;
+  int d = 0;
+  int storage = KNN_FP32;
+  int dp = 0;    // padded dimension of `rows`
+  int dp32 = 0;  // padded dimension of `master`
+  void* rows = nullptr;
+  float* rhalf = nullptr;
+  float* centre = nullptr;
+  float* master = nullptr;
+  int device = 0;
+  uint32_t magic = 0x6b6e6e52u;
+};
+
+namespace knn::host {
+
+// One search, as the pipeline sees it.
+struct SearchArgs {
+  const float* Q;        // caller's float32 queries [n][d]
+  int64_t n;
+  int d;
+  int64_t m;
+  const float* R32;      // one-shot form: caller's float32 references [m][d]; NULL for a handle
+  const void* rows;      // handle form: prepared rows for the tile kind
+  int ldr;
+  const float* rhalf;
+  const float* centre;
+  const void* canon;     // canonical rows for the exact re-rank
+  int canon_type;
+  int ld_canon;
+  int k;
+  int kprime;
+  int metric;
+  int kind;
+  float* dist;
+  int32_t* idx;
+  hipStream_t stream;
+};
+
+int fail(int status, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+#define HIP_TRY(expr, what)                            \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return ::knn::host::hip_fail(e_, what); \
+  } while (0)
+bool valid_refs(knn_refs_t r);
+int check_common(int64_t n, int64_t m, int32_t d, int32_t k, int32_t metric);
+
+// Fill `a` for a search of `refs` (argument checks included; returns a status).
+int refs_search_args(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32_t metric, int32_t precision,
+                     int32_t s_extra, float* dist, int32_t* idx, hipStream_t stream, SearchArgs* a);
+
+// Run one search in the caller's workspace; with ws == nullptr only the
+// needed size is stored in *need.
+int run_search_ws(const SearchArgs& a, void* ws, size_t ws_size, size_t* need);
+
+}  // namespace knn::host

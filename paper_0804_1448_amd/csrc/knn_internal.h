@@ -39,11 +39,12 @@ constexpr int kMaxGroups16 = 8;       // 16-bit MFMA k groups (32 dims) per chun
 constexpr int kMaxGroupsValu = 8;     // vector-ALU groups (16 dims) per chunk
 constexpr int kLdsBytes = 160 * 1024; // LDS per compute unit on gfx950
 
-// Parameters of the fused distance + top-k' selection kernel.
-struct FusedParams {
+// One search instance of the fused distance + top-k' selection kernel: a
+// query set against a reference set.
+struct FusedInst {
   const void* Q;        // prepared queries [n][ldq] (element type of the tile kind)
   const void* R;        // prepared references [m][ldr]
-  const float* rhalf;   // 0.5 * squared norm of each prepared reference (L2 only)
+  const float* rhalf;   // 0.5 * squared norm of each prepared reference (Euclidean only)
   uint64_t* part;       // out: per-slice sorted candidate lists [n][P][kc]
   int64_t n;
   int64_t m;
@@ -51,19 +52,38 @@ struct FusedParams {
   int ldq;              // row stride of Q, elements
   int ldr;              // row stride of R, elements
   int dp;               // padded dimension (multiple of the tile kind's k group)
-  int ng;               // k groups per chunk (the kernel's compile-time chunk width)
   int nchunk;           // ceil(dp / chunk width); the last chunk may be shorter
   int P;                // number of slices
   int kc;               // list capacity = k'
-  int cb;               // candidate buffer capacity per query
-  int waves;            // waves per workgroup
 };
 
-// Parameters of the merge + exact re-rank + finalize kernel.
-struct FinalParams {
+// One workgroup's share of a batched launch.
+struct FusedItem {
+  int inst;    // index into the instance table
+  int qblock;  // query block (waves * 16 queries)
+  int slice;   // reference slice
+  int pad;
+};
+
+// Launch parameters of the fused kernel.  With `items == nullptr` the grid is
+// (query blocks, slices) of the single instance `one`; otherwise workgroup b
+// processes items[b] of the instance table `insts`.
+struct FusedParams {
+  FusedInst one;
+  const FusedInst* insts;
+  const FusedItem* items;
+  int nitems;           // workgroups of a batched launch
+  int ng;               // k groups per chunk (the kernel's compile-time chunk width)
+  int cb;               // candidate buffer capacity per query (4 segments)
+  int waves;            // waves per workgroup
+  int kc_max;           // largest kc of the launch (sizes the LDS lists)
+};
+
+// One instance of the merge + exact re-rank + finalize kernel.
+struct FinalInst {
   const uint64_t* part; // [n][P][kc] sorted candidate lists (empty slots = kEmptyKey)
   const float* Q;       // original float32 queries [n][ldq]
-  const void* Rm;       // canonical reference rows [m][ldr] (float32 or float16)
+  const void* Rm;       // canonical reference rows [m][ldr]
   float* dist;          // out [n][k]
   int32_t* idx;         // out [n][k]
   int64_t n;
@@ -77,6 +97,37 @@ struct FinalParams {
   int kprime;           // candidates re-ranked (<= P * kc)
   int k;
   int metric;           // 0 L2, 1 L1, 2 Linf
+};
+
+// One finalize workgroup of a batched launch: kFinalWaves consecutive
+// queries of one instance.
+struct FinalItem {
+  int inst;
+  int q0;
+};
+
+struct FinalParams {
+  FinalInst one;
+  const FinalInst* insts;
+  const FinalItem* items;
+  int nitems;
+  int keys_max;         // largest P * kc of the launch
+  int kprime_max;       // largest k' of the launch
+  int p_max;            // largest P of the launch
+};
+
+// One array of a batched point preparation.
+struct PrepJob {
+  const float* src;     // [rows][lds] float32
+  void* dst;            // [rows][ldd] in element type `elem`
+  const float* centre;  // subtracted from every row, or NULL
+  float* rhalf;         // half squared norms of the stored rows, or NULL
+  int64_t rows;
+  int64_t row0;         // first global row of this job in the launch
+  int d;
+  int lds;
+  int ldd;
+  int elem;
 };
 
 constexpr int kFinalWaves = 4;          // queries per finalize workgroup
@@ -95,5 +146,7 @@ hipError_t launch_fused_f32hi(int ng, const FusedParams& p, hipStream_t stream);
 hipError_t launch_fused_half(int kind, int ng, const FusedParams& p, hipStream_t stream);
 hipError_t launch_fused_valu(int kind, int ng, const FusedParams& p, hipStream_t stream);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
+hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
+size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);
 
 }  // namespace knn

@@ -164,27 +164,41 @@ __device__ __forceinline__ float exact_distance(const float* q, const void* rm, 
   return (s0 + s1) + (s2 + s3);
 }
 
+__host__ __device__ inline size_t finalize_wave_bytes(int keys_max, int p_max, int kprime_max) {
+  return (((size_t)keys_max * 8 + (size_t)p_max * 4 + (size_t)kprime_max * 8) + 15) & ~(size_t)15;
+}
+
 __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t q = (int64_t)blockIdx.x * kFinalWaves + wave;
-  const int T = p.P * p.kc;
-  // per-wave region: keys[T] | lens[P] | cand[kprime] | cdist[kprime]
-  const size_t wave_bytes = (((size_t)T * 8 + (size_t)p.P * 4 + (size_t)p.kprime * 8) + 15) & ~(size_t)15;
+  FinalInst in;
+  int64_t q;
+  if (p.items) {
+    const FinalItem it = p.items[blockIdx.x];
+    in = p.insts[it.inst];
+    q = (int64_t)it.q0 + wave;
+  } else {
+    in = p.one;
+    q = (int64_t)blockIdx.x * kFinalWaves + wave;
+  }
+  const int T = in.P * in.kc;
+  // per-wave region: keys[T] | lens[P] | cand[kprime] | cdist[kprime], sized
+  // for the largest instance of the launch
+  const size_t wave_bytes = finalize_wave_bytes(p.keys_max, p.p_max, p.kprime_max);
   unsigned char* base = smem + wave * wave_bytes;
   uint64_t* keys = (uint64_t*)base;
   int* lens = (int*)(keys + T);
-  uint32_t* cand = (uint32_t*)(lens + p.P);
-  float* cdist = (float*)(cand + p.kprime);
-  if (q >= p.n) return;
+  uint32_t* cand = (uint32_t*)(lens + in.P);
+  float* cdist = (float*)(cand + in.kprime);
+  if (q >= in.n) return;
 
-  const uint64_t* src = p.part + q * (int64_t)T;
+  const uint64_t* src = in.part + q * (int64_t)T;
   for (int e = lane; e < T; e += 64) keys[e] = src[e];
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (int pl = lane; pl < p.P; pl += 64) {
-    const uint64_t* L = keys + pl * p.kc;
-    int lo = 0, hi = p.kc;
+  for (int pl = lane; pl < in.P; pl += 64) {
+    const uint64_t* L = keys + pl * in.kc;
+    int lo = 0, hi = in.kc;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (L[mid] != kEmptyKey) lo = mid + 1; else hi = mid;
@@ -195,17 +209,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
   __builtin_amdgcn_wave_barrier();
 
   int nvalid = 0;
-  for (int pl = 0; pl < p.P; ++pl) nvalid += lens[pl];
-  const int nc = min(p.kprime, nvalid);
+  for (int pl = 0; pl < in.P; ++pl) nvalid += lens[pl];
+  const int nc = min(in.kprime, nvalid);
 
   for (int e = lane; e < T; e += 64) {
-    const int pl = e / p.kc, i = e - pl * p.kc;
-    if (i >= lens[pl] || i >= p.kprime) continue;
+    const int pl = e / in.kc, i = e - pl * in.kc;
+    if (i >= lens[pl] || i >= in.kprime) continue;
     const uint64_t x = keys[e];
     int rank = i;
-    for (int o = 0; o < p.P && rank < p.kprime; ++o) {
+    for (int o = 0; o < in.P && rank < in.kprime; ++o) {
       if (o == pl) continue;
-      const uint64_t* L = keys + o * p.kc;
+      const uint64_t* L = keys + o * in.kc;
       int lo = 0, hi = lens[o];
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -213,15 +227,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
       }
       rank += lo;
     }
-    if (rank < p.kprime) cand[rank] = (uint32_t)x;
+    if (rank < in.kprime) cand[rank] = (uint32_t)x;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 
-  const float* qrow = p.Q + q * (int64_t)p.ldq;
+  const float* qrow = in.Q + q * (int64_t)in.ldq;
   for (int j = lane; j < nc; j += 64) {
     const uint32_t r = cand[j];
-    cdist[j] = r < (uint64_t)p.m ? exact_distance(qrow, p.Rm, p.rm_type, (int64_t)r * p.ldr, p.d, p.metric)
+    cdist[j] = r < (uint64_t)in.m ? exact_distance(qrow, in.Rm, in.rm_type, (int64_t)r * in.ldr, in.d, in.metric)
                                  : __builtin_huge_valf();
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -235,9 +249,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
       const float di = cdist[i];
       rank += (di < dj) || (di == dj && cand[i] < rj);
     }
-    if (rank < p.k) {
-      p.dist[q * p.k + rank] = p.metric == 0 ? sqrtf(dj) : dj;
-      p.idx[q * p.k + rank] = (int32_t)rj;
+    if (rank < in.k) {
+      in.dist[q * in.k + rank] = in.metric == 0 ? sqrtf(dj) : dj;
+      in.idx[q * in.k + rank] = (int32_t)rj;
     }
   }
 }
@@ -250,11 +264,62 @@ hipError_t launch_finalize(const FinalParams& p, hipStream_t stream) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (p.n <= 0) return hipSuccess;
-  const int T = p.P * p.kc;
-  const size_t wave_bytes = (((size_t)T * 8 + (size_t)p.P * 4 + (size_t)p.kprime * 8) + 15) & ~(size_t)15;
-  dim3 grid((unsigned)((p.n + kFinalWaves - 1) / kFinalWaves)), block(kFinalWaves * kWaveSize);
-  hipLaunchKernelGGL(finalize_kernel, grid, block, wave_bytes * kFinalWaves, stream, p);
+  const unsigned blocks = p.items ? (unsigned)p.nitems : (unsigned)((p.one.n + kFinalWaves - 1) / kFinalWaves);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(kFinalWaves * kWaveSize),
+                     finalize_lds_bytes(p.keys_max, p.p_max, p.kprime_max), stream, p);
+  return hipGetLastError();
+}
+
+size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max) {
+  return finalize_wave_bytes(keys_max, p_max, kprime_max) * kFinalWaves;
+}
+
+// ------------------------------------------------ batched point preparation
+// One wave per row over the concatenated rows of several arrays; a row's
+// job is found by binary search over the jobs' first rows.
+__global__ __launch_bounds__(256) void prep_batched_kernel(const PrepJob* __restrict__ jobs, int njobs,
+                                                           int64_t total_rows) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (g >= total_rows) return;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].row0 <= g) lo = mid; else hi = mid - 1;
+  }
+  const PrepJob jb = jobs[lo];
+  const int64_t row = g - jb.row0;
+  const float* s = jb.src + row * (int64_t)jb.lds;
+  float acc = 0.f;
+  for (int t = lane; t < jb.ldd; t += 64) {
+    const float v = t < jb.d ? (jb.centre ? s[t] - jb.centre[t] : s[t]) : 0.f;
+    float stored;
+    if (jb.elem == ELEM_F32) {
+      ((float*)jb.dst)[row * jb.ldd + t] = v;
+      stored = v;
+    } else if (jb.elem == ELEM_BF16) {
+      const uint16_t b = f32_to_bf16_rne(v);
+      ((uint16_t*)jb.dst)[row * jb.ldd + t] = b;
+      stored = bf16_to_f32(b);
+    } else {
+      const uint16_t b = f32_to_f16_rne(v);
+      ((uint16_t*)jb.dst)[row * jb.ldd + t] = b;
+      stored = f16_to_f32(b);
+    }
+    acc += stored * stored;
+  }
+  if (jb.rhalf) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) jb.rhalf[row] = 0.5f * acc;
+  }
+}
+
+hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream) {
+  if (total_rows <= 0 || njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prep_batched_kernel, dim3((unsigned)((total_rows + 3) / 4)), dim3(256), 0, stream, jobs_dev, njobs,
+                     total_rows);
   return hipGetLastError();
 }
 

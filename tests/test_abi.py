@@ -102,3 +102,19 @@ def test_last_error_is_thread_local(lib):
     t.join()
     assert seen["msg"] == ""
     assert "k" in lib.knn_last_error().decode()
+
+
+def test_batch_create_rejects_bad_arguments(lib):
+    import paper_0804_1448_amd._lib as L
+
+    h = ctypes.c_void_p()
+    assert lib.knn_batch_create(None, 1, 0, -1, 0, ctypes.byref(h)) == -1
+    assert lib.knn_batch_create(None, -1, 0, -1, 0, ctypes.byref(h)) == -1
+    arr = (L.Problem * 1)()
+    arr[0] = L.Problem(None, 0x1000, 4, 2, 0, 0x1000, 0x1000)
+    assert lib.knn_batch_create(arr, 1, 0, -1, 0, ctypes.byref(h)) == -1
+    assert "instance 0" in lib.knn_last_error().decode()
+    assert lib.knn_batch_create(arr, 1, 9, -1, 0, ctypes.byref(h)) == -1
+    assert lib.knn_batch_run(None, 0, None) == -1
+    assert lib.knn_batch_destroy(None) == -1
+    assert not h.value
