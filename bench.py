@@ -1,18 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the brute-force k-NN path on one MI355X.
 
-A step is one pass of the whole path over the workload: for each distance of
-the workload, knn_search (reference preparation, query preparation, fused
-distance tiles + per-query selection, slice merge, exact re-rank and output)
-on float32 inputs already resident in device memory.  The default workload
-is 16384 references and 16384 queries in 96 dimensions from a 64-component
-Gaussian mixture, k = 20, searched with the Euclidean distance (matrix cores)
-and the Manhattan distance (vector ALUs).
+Default mode (``--mode pairs``): a step is one pass of the whole path over the
+workload: for each distance of the workload, knn_search (reference
+preparation, query preparation, fused distance tiles + per-query selection,
+slice merge, exact re-rank and output) on float32 inputs already resident in
+device memory.  The default workload is 16384 references and 16384 queries
+in 96 dimensions from a 64-component Gaussian mixture, k = 20, searched with
+the Euclidean distance (matrix cores) and the Manhattan distance (vector
+ALUs).
 
 Prints one JSON line.  Besides the throughput it reports the roofline of the
 dominant kernel (its average duration measured with HIP events on the stream
 it runs on) and the FP64 oracle timed on the host cores over a query sample,
 which also checks the GPU result on that sample.
+
+Other modes print one JSON line each, for the method's other forms:
+  --mode precision  2^20 references, 65536 queries, d = 128, k = 32: BF16
+                    tiles + 32 extra candidates + exact FP32 re-rank, against
+                    the plain FP32 search on the same GPU and the oracle.
+  --mode batched    512 independent instances (uneven m, n, d, k) in a few
+                    launches, FP16 tiles + re-rank, autotuned, graph replay.
+  --mode serve      four resident FP16 sets (1-4 Mi points, d = 128), Poisson
+                    arrivals of 1..2048-query requests; QPS and p50/p99
+                    latency, against the same trace on FP32 sets.
+  --mode copy       a plain 1 GiB device copy: the HBM reference against which
+                    the FETCH_SIZE / WRITE_SIZE counters are calibrated.
 """
 from __future__ import annotations
 
@@ -20,6 +33,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 # peaks of one MI355X (vendor figures)
@@ -40,15 +54,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_roofline(name: str, avg_s: float, n: int, m: int, d: int):
-    """Algorithmic work of one fused launch over n x m pairs, against its peak."""
+def kernel_roofline(name: str, avg_s: float, pairs: float, d: float):
+    """Algorithmic work of one fused launch over ``pairs`` query-reference pairs, against its peak."""
     if name.startswith("fused_l2"):
-        flops = 2.0 * d * n * m  # cross term q.r: d multiply-adds per pair
+        flops = 2.0 * d * pairs  # cross term q.r: d multiply-adds per pair
         peak = PEAK_FP32_MFMA_TFLOPS if name.endswith("f32") else PEAK_BF16_MFMA_TFLOPS
         ach = flops / avg_s / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                 "traffic": None, "kernel": name, "avg_ms": avg_s * 1e3, "work_per_launch": flops}
-    ops = 2.0 * d * n * m  # one subtract + one absolute accumulate (sum or max) per pair and dimension
+    ops = 2.0 * d * pairs  # one subtract + one absolute accumulate (sum or max) per pair and dimension
     ach = ops / avg_s / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TOPS,
             "traffic": None, "kernel": name, "avg_ms": avg_s * 1e3, "work_per_launch": ops}
@@ -65,30 +79,65 @@ def host_threads() -> int:
     return max(1, n)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
-    args = ap.parse_args()
+def kernel_table(K):
+    return {name: {"avg_ms": tot / cnt, "launches": cnt, "total_ms": tot} for name, (tot, cnt) in K.timing.all().items()}
 
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
-              "across GPUs in this build)", file=sys.stderr)
-        sys.exit(2)
 
+def timed(K, torch, fn, steps, warmup):
+    """Run ``fn`` warmup + steps times; return (seconds per step, kernel table of the timed steps)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    K.timing.reset()
+    K.timing.enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    K.timing.enable(False)
+    return (t1 - t0) / steps, kernel_table(K)
+
+
+def oracle_sample(Q, R, k, metrics, target_s, seed=12345, max_rows=None):
+    """Time the oracle on a query sample sized to about ``target_s`` host seconds."""
     import numpy as np
+
+    import oracle
+
+    threads = host_threads()
+    n = Q.shape[0]
+    rng = np.random.default_rng(seed)
+    probe = rng.choice(n, size=min(n, 16), replace=False)
+    tp = time.perf_counter()
+    for mt in metrics:
+        oracle.knn(Q[probe], R, k, mt, threads=threads)
+    per_query = (time.perf_counter() - tp) / len(probe)
+    nsamp = int(min(n, max(len(probe), target_s / max(per_query, 1e-9))))
+    if max_rows:
+        nsamp = min(nsamp, max_rows)
+    rows = np.sort(rng.choice(n, size=nsamp, replace=False))
+    log(f"[bench] oracle sample: {nsamp} queries x {R.shape[0]} references x {len(metrics)} distances, "
+        f"{threads} threads")
+    tc = time.perf_counter()
+    refs = {mt: oracle.knn(Q[rows], R, k, mt, threads=threads) for mt in metrics}
+    cpu_s = time.perf_counter() - tc
+    return rows, refs, cpu_s, threads
+
+
+def parity_summary(rep):
+    return {kk: rep[kk] for kk in ("ok", "max_rel_err", "max_rel_err_hits", "recall", "recall_tie", "bad_dist",
+                                   "bad_idx", "queries")}
+
+
+# ------------------------------------------------------------------ pairs
+def bench_pairs(args):
     import torch
 
     import paper_0804_1448_amd as K
     import synthdata
 
-    K.load()
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     R, Q, p = synthdata.workload(args.workload)
     n, m, d, k = p["n"], p["m"], p["d"], p["k"]
@@ -103,33 +152,16 @@ def main():
             K.search(Qd, Rd, k, mt, out=outs[mt])
 
     log(f"[bench] workload {args.workload}: n={n} m={m} d={d} k={k} metrics={metrics}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    K.timing.reset()
-    K.timing.enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    K.timing.enable(False)
-    kern = K.timing.all()
-    ms_per_step = (t1 - t0) / args.steps * 1e3
+    sec, kernels = timed(K, torch, step, args.steps, args.warmup)
+    ms_per_step = sec * 1e3
     pairs_per_step = float(n) * m * len(metrics)
-    value = pairs_per_step / (ms_per_step / 1e3)
+    value = pairs_per_step / sec
     log(f"[bench] {args.steps} steps: {ms_per_step:.4f} ms/step, {value:.4e} pairs/s")
-    kernels = {name: {"avg_ms": tot / cnt, "launches": cnt, "total_ms": tot} for name, (tot, cnt) in kern.items()}
     for name, v in kernels.items():
         log(f"[bench]   {name:16s} avg {v['avg_ms']:.4f} ms x {v['launches']}")
-
-    rooflines = {}
-    for name, v in kernels.items():
-        if name.startswith("fused_"):
-            rooflines[name] = kernel_roofline(name, v["avg_ms"] / 1e3, n, m, d)
+    rooflines = {name: kernel_roofline(name, v["avg_ms"] / 1e3, float(n) * m, d)
+                 for name, v in kernels.items() if name.startswith("fused_")}
     dominant = max(rooflines, key=lambda nm: kernels[nm]["total_ms"])
-    roof = dict(rooflines[dominant])
 
     result = {
         "metric": "query-ref pairs/sec",
@@ -147,46 +179,402 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "k": k, "distances": metrics,
                    "data": (f"{p['comps']}-component isotropic Gaussian mixture, sigma {p['sigma']}"
                             if p["kind"] == "gmm" else "uniform [0,1)")},
-        "roofline": roof,
+        "roofline": dict(rooflines[dominant]),
         "rooflines": rooflines,
         "kernels": kernels,
     }
-
     if not args.no_cpu_baseline:
-        import oracle
         from oracle.check import compare
 
-        threads = host_threads()
-        rng = np.random.default_rng(12345)
-        # calibrate: time a small sample, then size the sample to the target host time
-        probe = rng.choice(n, size=min(n, 16), replace=False)
-        tp = time.perf_counter()
-        for mt in metrics:
-            oracle.knn(Q[probe], R, k, mt, threads=threads)
-        per_query = (time.perf_counter() - tp) / len(probe)
-        nsamp = int(min(n, max(len(probe), args.cpu_seconds / max(per_query, 1e-9))))
-        rows = np.sort(rng.choice(n, size=nsamp, replace=False))
-        log(f"[bench] oracle sample: {nsamp} queries x {m} references x {len(metrics)} distances, {threads} threads")
-        tc = time.perf_counter()
-        refs = {mt: oracle.knn(Q[rows], R, k, mt, threads=threads) for mt in metrics}
-        cpu_s = time.perf_counter() - tc
-        cpu_value = float(nsamp) * m * len(metrics) / cpu_s
+        rows, refs, cpu_s, threads = oracle_sample(Q, R, k, metrics, args.cpu_seconds)
         parity = {}
         for mt in metrics:
-            dist = outs[mt][0].cpu().numpy()
-            idx = outs[mt][1].cpu().numpy()
-            rep = compare(Q, R, k, mt, dist, idx, tol=1e-5, ref=refs[mt], rows=rows)
-            parity[mt] = {kk: rep[kk] for kk in ("ok", "max_rel_err", "recall", "recall_tie", "bad_dist", "bad_idx",
-                                                   "queries")}
+            rep = compare(Q, R, k, mt, outs[mt][0].cpu().numpy(), outs[mt][1].cpu().numpy(), tol=1e-5,
+                          ref=refs[mt], rows=rows)
+            parity[mt] = parity_summary(rep)
         result["cpu_baseline"] = {
-            "value": cpu_value, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nsamp} seeded queries of {n} against all {m} references, distances {metrics}, "
+            "value": float(len(rows)) * m * len(metrics) / cpu_s, "unit": "pairs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(rows)} seeded queries of {n} against all {m} references, distances {metrics}, "
                       f"FP64 brute force (select mode), {cpu_s:.2f} s",
         }
         result["parity_vs_oracle"] = parity
         result["recall_at_k"] = {mt: parity[mt]["recall"] for mt in metrics}
+    return result
 
-    print(json.dumps(result), flush=True)
+
+# -------------------------------------------------------------- precision
+def bench_precision(args):
+    import numpy as np
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    p = dict(synthdata.WORKLOADS["gmm1m_d128"])
+    n, m, d, k = p["n"], p["m"], p["d"], p["k"]
+    th = host_threads()
+    t0 = time.perf_counter()
+    R = synthdata.gmm(m, d, p["comps"], p["sigma"], p["wid"], synthdata.ROLE_REFS, threads=th)
+    Q = synthdata.gmm(n, d, p["comps"], p["sigma"], p["wid"], synthdata.ROLE_QUERIES, threads=th)
+    log(f"[bench] precision workload: n={n} m={m} d={d} k={k}, generated in {time.perf_counter() - t0:.1f} s")
+    Rd = torch.from_numpy(R).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    refs16 = K.Refs(Rd, storage="bf16", keep_fp32_master=True)
+    refs32 = K.Refs(Rd, storage="fp32")
+    del Rd
+    out16 = (torch.empty((n, k), dtype=torch.float32, device="cuda"), torch.empty((n, k), dtype=torch.int32,
+                                                                                  device="cuda"))
+    out32 = (torch.empty_like(out16[0]), torch.empty_like(out16[1]))
+    s_extra = 32
+    sec16, kern16 = timed(K, torch, lambda: refs16.search(Qd, k, "l2", precision="bf16", s_extra=s_extra,
+                                                          out=out16), args.steps, args.warmup)
+    sec32, kern32 = timed(K, torch, lambda: refs32.search(Qd, k, "l2", precision="fp32", out=out32),
+                          args.steps, args.warmup)
+    pairs = float(n) * m
+    log(f"[bench] bf16+rerank {sec16 * 1e3:.2f} ms ({pairs / sec16:.4e} pairs/s), fp32 {sec32 * 1e3:.2f} ms "
+        f"({pairs / sec32:.4e} pairs/s)")
+    for tag, kt in (("bf16", kern16), ("fp32", kern32)):
+        for name, v in kt.items():
+            log(f"[bench]   {tag} {name:16s} avg {v['avg_ms']:.4f} ms x {v['launches']}")
+    roof16 = kernel_roofline("fused_l2_bf16", kern16["fused_l2_bf16"]["avg_ms"] / 1e3, pairs, d)
+    roof32 = kernel_roofline("fused_l2_f32", kern32["fused_l2_f32"]["avg_ms"] / 1e3, pairs, d)
+    result = {
+        "metric": "query-ref pairs/sec",
+        "value": pairs / sec16,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec16 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 tiles, f32 accumulate + f32 re-rank",
+        "data": "synthetic",
+        "config": {"workload": "gmm1m_d128", "n": n, "m": m, "d": d, "k": k, "s_extra": s_extra,
+                   "data": f"{p['comps']}-component isotropic Gaussian mixture, sigma {p['sigma']}"},
+        "fp32": {"value": pairs / sec32, "ms_per_step": sec32 * 1e3, "roofline": roof32},
+        "speedup_vs_fp32": sec32 / sec16,
+        "roofline": roof16,
+        "kernels": {"bf16": kern16, "fp32": kern32},
+    }
+    if not args.no_cpu_baseline:
+        from oracle.check import compare
+
+        rows, refs, cpu_s, threads = oracle_sample(Q, R, k, ["l2"], args.cpu_seconds, max_rows=512)
+        rep16 = compare(Q, R, k, "l2", out16[0].cpu().numpy(), out16[1].cpu().numpy(), tol=1e-5, ref=refs["l2"],
+                        rows=rows)
+        rep32 = compare(Q, R, k, "l2", out32[0].cpu().numpy(), out32[1].cpu().numpy(), tol=1e-5, ref=refs["l2"],
+                        rows=rows)
+        result["parity_vs_oracle"] = {"bf16": parity_summary(rep16), "fp32": parity_summary(rep32)}
+        result["recall_at_k"] = {"bf16": rep16["recall"], "fp32": rep32["recall"]}
+        result["cpu_baseline"] = {
+            "value": float(len(rows)) * m / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(rows)} seeded queries of {n} against all {m} references, Euclidean, FP64 brute force "
+                      f"(select mode), {cpu_s:.2f} s",
+        }
+    refs16.close()
+    refs32.close()
+    return result
+
+
+# ---------------------------------------------------------------- batched
+def bench_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    specs = synthdata.batch_specs(count=args.instances)
+    th = host_threads()
+    t0 = time.perf_counter()
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(th) as ex:
+        data = list(ex.map(lambda a: synthdata.batch_instance(a[0], a[1][0], a[1][1], a[1][2]),
+                           enumerate(specs)))
+    log(f"[bench] batched workload: {len(specs)} instances generated in {time.perf_counter() - t0:.1f} s")
+    probs, keep = [], []
+    for (m, n, d, k), (R, Q) in zip(specs, data):
+        Rd = torch.from_numpy(R).cuda()
+        refs = K.Refs(Rd, storage="fp16", keep_fp32_master=True)
+        Qd = torch.from_numpy(Q).cuda()
+        probs.append((refs, Qd, k, "l2"))
+        keep.append(refs)
+        del Rd
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = K.Batch(probs, "fp16", tune=True)
+    b.run()
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    sec, kern = timed(K, torch, lambda: b.run(use_graph=True), args.steps, args.warmup)
+    pairs = float(sum(m * n for m, n, _, _ in specs))
+    flops = float(sum(2.0 * m * n * d for m, n, d, _ in specs))
+    log(f"[bench] batched: {sec * 1e3:.2f} ms/step, {pairs / sec:.4e} pairs/s (tune + first run {tune_s:.1f} s)")
+    # eager run, kernel by kernel, for the per-kernel roofline
+    sec_e, kern_e = timed(K, torch, lambda: b.run(use_graph=False), max(1, args.steps // 2), 1)
+    for name, v in kern_e.items():
+        log(f"[bench]   eager {name:16s} avg {v['avg_ms']:.4f} ms x {v['launches']}")
+    fused_ms = kern_e.get("fused_l2_f16", {"total_ms": float("nan")})["total_ms"] / max(1, args.steps // 2)
+    ach = flops / (fused_ms / 1e3) / 1e12
+    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_BF16_MFMA_TFLOPS, "traffic": None, "kernel": "fused_l2_f16",
+            "avg_ms": fused_ms, "work_per_launch": flops, "note": "all fused launches of one step summed"}
+    result = {
+        "metric": "query-ref pairs/sec",
+        "value": pairs / sec,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 tiles, f32 accumulate + f32 re-rank",
+        "data": "synthetic",
+        "config": {"workload": f"batch{len(specs)}", "instances": len(specs), "pairs": pairs,
+                   "m": [1000, 200000], "n": [16, 4096], "d": [16, 32, 64, 128], "k": [1, 8, 32, 100],
+                   "graph": True, "tuned": True, "data": "uniform [0,1)"},
+        "eager_ms_per_step": sec_e * 1e3,
+        "roofline": roof,
+        "kernels": {"graph": kern, "eager": kern_e},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.check import compare
+
+        rng = np.random.default_rng(7)
+        pick = rng.choice(len(specs), size=min(len(specs), 24), replace=False)
+        outs = b.results()
+        recalls, ok, worst = [], True, 0.0
+        tc = time.perf_counter()
+        qsum = 0
+        for i in pick:
+            m, n, d, k = specs[i]
+            R, Q = data[i]
+            rows = np.sort(rng.choice(n, size=min(n, 8), replace=False))
+            ref = oracle.knn(Q[rows], R, k, "l2", threads=th)
+            qsum += len(rows) * m
+            rep = compare(Q, R, k, "l2", outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy(), tol=1e-5, ref=ref,
+                          rows=rows)
+            recalls.append(rep["recall"])
+            worst = max(worst, rep["max_rel_err_hits"])
+        cpu_s = time.perf_counter() - tc
+        result["recall_at_k"] = float(np.mean(recalls))
+        result["parity_vs_oracle"] = {"instances": len(pick), "queries_per_instance": 8,
+                                      "min_recall": float(np.min(recalls)), "max_rel_err_hits": worst}
+        result["cpu_baseline"] = {"value": qsum / cpu_s, "unit": "pairs/s", "cores": th, "kind": "oracle",
+                                  "sample": f"8 queries of each of {len(pick)} sampled instances, FP64 brute force"}
+    b.close()
+    for r in keep:
+        r.close()
+    return result
+
+
+# ------------------------------------------------------------------ serve
+def run_trace(K, srv, pools, trace, rate, timeout_s=120.0):
+    """Submit ``trace`` at ``rate`` requests/s (open loop); return latencies (us) and wall time."""
+    import numpy as np
+
+    tickets = []
+    lock = threading.Lock()
+    done_submitting = threading.Event()
+    lat = []
+    rejected = [0]
+
+    def waiter():
+        i = 0
+        while True:
+            with lock:
+                have = i < len(tickets)
+                t = tickets[i] if have else None
+            if have:
+                _, _, l = srv.wait(t)
+                lat.append(l)
+                i += 1
+            elif done_submitting.is_set():
+                with lock:
+                    if i >= len(tickets):
+                        return
+            else:
+                time.sleep(0.0002)
+
+    w = threading.Thread(target=waiter)
+    w.start()
+    t0 = time.perf_counter()
+    due = t0
+    for gap, s, off, n, k in trace:
+        due += gap / rate
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        while True:
+            try:
+                t = srv.submit(s, pools[s][off:off + n], k)
+                break
+            except K.KnnError as e:
+                if e.status != -5:
+                    raise
+                rejected[0] += 1
+                time.sleep(0.0005)
+        with lock:
+            tickets.append(t)
+        if time.perf_counter() - t0 > timeout_s:
+            break
+    done_submitting.set()
+    w.join()
+    wall = time.perf_counter() - t0
+    return np.array(lat), wall, len(tickets), rejected[0]
+
+
+def bench_serve(args):
+    import numpy as np
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    spec = dict(synthdata.SERVE4)
+    th = host_threads()
+    t0 = time.perf_counter()
+    sets32, sets16, pools = [], [], []
+    for j in range(len(spec["sets"])):
+        R = synthdata.serve_set(j, spec, threads=th)
+        Rd = torch.from_numpy(R).cuda()
+        sets16.append(K.Refs(Rd, storage="fp16", keep_fp32_master=False))
+        sets32.append(K.Refs(Rd, storage="fp32"))
+        del Rd, R
+        pools.append(synthdata.serve_queries(j, spec))
+    torch.cuda.synchronize()
+    log(f"[bench] serving sets {spec['sets']} d={spec['d']} ready in {time.perf_counter() - t0:.1f} s")
+    trace = synthdata.serve_requests(args.requests, spec, sizes=args.sizes)
+    skip = len(trace) // 20  # the first 5% of each run are warm-up
+    mean_pairs = float(np.mean([n * spec["sets"][s] for _, s, _, n, _ in trace]))
+    out = {}
+    for tag, sets, prec in (("fp16", sets16, "fp16"), ("fp32", sets32, "fp32")):
+        srv = K.Server(sets, mem_budget=args.serve_mem << 30, max_batches=4, max_queue=4096,
+                       max_batch_queries=8192, precision=prec)
+        # capacity: closed loop over the first requests, all submitted at once
+        cal = trace[: min(len(trace), 200)]
+        _, wall_c, cnt_c, _ = run_trace(K, srv, pools, cal, rate=1e9)
+        capacity = cnt_c / wall_c
+        res = {"capacity_rps": capacity}
+        for load in args.loads:
+            rate = load * capacity
+            lat, wall, cnt, rej = run_trace(K, srv, pools, trace, rate)
+            lat = lat[skip:]
+            res[f"load{load:g}"] = {
+                "offered_rps": rate, "qps": cnt / wall, "queries_per_s": float(sum(n for _, _, _, n, _ in
+                                                                                    trace[:cnt])) / wall,
+                "p50_ms": float(np.percentile(lat, 50)) / 1e3, "p99_ms": float(np.percentile(lat, 99)) / 1e3,
+                "mean_ms": float(lat.mean()) / 1e3, "requests": cnt, "warmup_requests": skip,
+                "busy_retries": rej}
+            log(f"[bench] serve {tag} load {load:g}: {res[f'load{load:g}']}")
+        res["stats"] = srv.stats()
+        srv.close()
+        out[tag] = res
+    # parity of the serving path on a few requests against the oracle
+    result = {
+        "metric": "serving p50/p99 latency",
+        "value": out["fp16"][f"load{args.loads[0]:g}"]["p99_ms"],
+        "unit": "ms (p99)",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 200,
+        "ms_per_step": None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16 tiles, f32 accumulate + f32 re-rank",
+        "data": "synthetic",
+        "config": {"workload": "serve4_d128", "sets": list(spec["sets"]), "d": spec["d"],
+                   "request_queries": list(spec["n"]), "sizes": args.sizes, "k": list(spec["k"]),
+                   "arrivals": "Poisson",
+                   "mem_budget_gib": args.serve_mem, "mean_pairs_per_request": mean_pairs},
+        "serve": out,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.check import compare
+
+        srv = K.Server(sets16, mem_budget=args.serve_mem << 30, precision="fp16")
+        recalls, worst = [], 0.0
+        for gap, s, off, n, k in trace[:6]:
+            nn = min(n, 4)
+            Q = pools[s][off:off + nn]
+            dist, idx, _ = srv.wait(srv.submit(s, Q, k))
+            R = synthdata.serve_set(s, spec, threads=th)
+            rep = compare(Q, R, k, "l2", dist, idx, tol=1e-5, ref=oracle.knn(Q, R, k, "l2", threads=th))
+            recalls.append(rep["recall"])
+            worst = max(worst, rep["max_rel_err_hits"])
+        srv.close()
+        result["recall_at_k"] = float(np.mean(recalls))
+        result["parity_vs_oracle"] = {"requests": len(recalls), "min_recall": float(np.min(recalls)),
+                                      "max_rel_err_hits": worst}
+    for r in sets16 + sets32:
+        r.close()
+    return result
+
+
+# ------------------------------------------------------------------- copy
+def bench_copy(args):
+    import torch
+
+    nbytes = 1 << 30
+    src = torch.rand(nbytes // 4, device="cuda")
+    dst = torch.empty_like(src)
+    sec, _ = timed(__import__("paper_0804_1448_amd"), torch, lambda: dst.copy_(src), args.steps, args.warmup)
+    gbs = 2.0 * nbytes / sec / 1e9
+    log(f"[bench] copy {nbytes} bytes: {sec * 1e3:.3f} ms, {gbs:.1f} GB/s (read + write)")
+    return {"metric": "device copy bandwidth", "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "copy1g", "bytes_read": nbytes, "bytes_written": nbytes},
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "traffic": None}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy"])
+    ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
+    ap.add_argument("--instances", type=int, default=512, help="batched mode: number of instances")
+    ap.add_argument("--requests", type=int, default=10000, help="serve mode: requests per trace")
+    ap.add_argument("--sizes", default="uniform", choices=["uniform", "loguniform"],
+                    help="serve mode: request size distribution")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8], help="serve mode: fractions of capacity")
+    ap.add_argument("--serve-mem", type=int, default=8, help="serve mode: request memory budget, GiB")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
+              "across GPUs in this build)", file=sys.stderr)
+        sys.exit(2)
+    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3)}
+    if args.steps is None:
+        args.steps = defaults[args.mode][0]
+    if args.warmup is None:
+        args.warmup = defaults[args.mode][1]
+
+    import torch
+
+    import paper_0804_1448_amd as K
+
+    K.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    fn = {"pairs": bench_pairs, "precision": bench_precision, "batched": bench_batched, "serve": bench_serve,
+          "copy": bench_copy}
+    print(json.dumps(fn[args.mode](args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libknn.so")
-SOURCES = ["knn_kernels.hip", "knn_fused_f32lo.hip", "knn_fused_f32hi.hip", "knn_fused_half.hip",
-           "knn_fused_valu.hip", "knn_api.cpp", "knn_server.cpp"]
+SOURCES = ["knn_kernels.hip", "knn_api.cpp", "knn_server.cpp"] + [
+    f"knn_fused_{unit}_{v}.hip" for unit in ("f32lo", "f32hi", "bf16", "f16", "l1", "linf") for v in ("s", "l")]
 
 # Packed float32 instructions are disabled on purpose: the compiler emits
 # them by itself from ordinary float code, and this library does not use them.

@@ -197,7 +197,7 @@ int device_cu_count() {
 }
 
 // Environment overrides of the launch plan, for tuning sweeps: KNN_FUSED_WAVES,
-// KNN_FUSED_CB, KNN_FUSED_CW, KNN_FUSED_P.  A value the plan cannot honour is
+// KNN_FUSED_CB, KNN_FUSED_NG, KNN_FUSED_P.  A value the plan cannot honour is
 // ignored.
 int env_int(const char* name) {
   const char* v = getenv(name);
@@ -668,7 +668,7 @@ std::vector<std::pair<int, int>> group_configs(const BatchGroup& g) {
   return out;
 }
 
-// tuned configurations of this process (and of a JSON cache file when
+// tuned configurations of this process (and of a text cache file when
 // KNN_TUNE_CACHE names one), keyed by "kind/dp/kclass/size bucket"
 std::mutex g_tune_mutex;
 std::map<std::string, std::pair<int, int>> g_tune;
@@ -1114,10 +1114,17 @@ int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream) {
       timing = g_tm_enabled;
       g_tm_enabled = false;
     }
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    st = batch_enqueue(*batch, s);
+    // capture on a private stream (the caller's may be the null stream,
+    // which cannot be captured); replays go to the caller's stream
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) {
+      st = batch_enqueue(*batch, cs);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
     {
       std::lock_guard<std::mutex> lock(g_tm_mutex);
       g_tm_enabled = timing;
@@ -1126,7 +1133,10 @@ int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream) {
       if (graph) (void)hipGraphDestroy(graph);
       return st;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(e, "graph capture");
+    }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {

@@ -124,8 +124,12 @@ __device__ __forceinline__ void merge_ranked(uint64_t* L, const Segs& b, int len
 }
 
 // ------------------------------------------------ register bitonic merge
-// Cross-lane exchange with lane ^ J: DPP moves for J <= 8 (quad permutes,
-// row shifts, row rotate), ds_bpermute for J = 16, 32.
+// Cross-lane exchange with lane ^ J, all on the vector ALU: DPP moves for
+// J <= 8 (quad permutes, row shifts, row rotate); for J = 16 and 32 the
+// gfx950 lane-swap instructions.  v_permlane16_swap with both operands equal
+// to v leaves v's even 16-lane rows in the first result and its odd rows in
+// the second, each row duplicated over its pair; v_permlane32_swap does the
+// same for 32-lane halves.  A lane then takes the copy of its partner row.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
@@ -140,7 +144,14 @@ __device__ __forceinline__ uint32_t xor_lane32(uint32_t v, int lane) {
     const uint32_t dn = dpp_mov<0x114>(v);              // row_shr:4 (from lane - 4)
     return (lane & 4) ? dn : up;
   } else if constexpr (J == 8) return dpp_mov<0x128>(v);  // row_ror:8
-  else return (uint32_t)__shfl_xor((int)v, J);
+  else if constexpr (J == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? r[0] : r[1];
+  } else {
+    static_assert(J == 32, "lane distance");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? r[0] : r[1];
+  }
 }
 
 template <int J>
@@ -160,8 +171,8 @@ __device__ __forceinline__ uint64_t bitonic_step(uint64_t v, int lane, bool asce
   return (lt == keep_min) ? v : o;
 }
 
-// sort one key per lane ascending over the 64 lanes
-__device__ __forceinline__ uint64_t bitonic_sort64(uint64_t v, int lane) {
+// sort one key per lane over the 64 lanes, ascending or descending
+__device__ __forceinline__ uint64_t bitonic_sort64(uint64_t v, int lane, bool descending) {
   v = bitonic_step<1>(v, lane, (lane & 2) == 0);
   v = bitonic_step<2>(v, lane, (lane & 4) == 0);
   v = bitonic_step<1>(v, lane, (lane & 4) == 0);
@@ -177,12 +188,13 @@ __device__ __forceinline__ uint64_t bitonic_sort64(uint64_t v, int lane) {
   v = bitonic_step<4>(v, lane, (lane & 32) == 0);
   v = bitonic_step<2>(v, lane, (lane & 32) == 0);
   v = bitonic_step<1>(v, lane, (lane & 32) == 0);
-  v = bitonic_step<32>(v, lane, true);
-  v = bitonic_step<16>(v, lane, true);
-  v = bitonic_step<8>(v, lane, true);
-  v = bitonic_step<4>(v, lane, true);
-  v = bitonic_step<2>(v, lane, true);
-  v = bitonic_step<1>(v, lane, true);
+  const bool up = !descending;
+  v = bitonic_step<32>(v, lane, up);
+  v = bitonic_step<16>(v, lane, up);
+  v = bitonic_step<8>(v, lane, up);
+  v = bitonic_step<4>(v, lane, up);
+  v = bitonic_step<2>(v, lane, up);
+  v = bitonic_step<1>(v, lane, up);
   return v;
 }
 
@@ -199,10 +211,9 @@ __device__ __forceinline__ uint64_t bitonic_clean64(uint64_t v, int lane) {
 
 // Merge of a list of len <= kc <= 64 keys with a buffer of at most 64 keys
 // held one per lane: lane j loads buffer key j (segment j / 16, entry
-// j % 16).  The buffer is sorted across the wave; since the list is sorted
-// ascending and the sorted buffer read in reverse lane order is descending,
-// their elementwise minimum holds the 64 smallest keys of the union as a
-// bitonic sequence, which six exchange stages sort.
+// j % 16).  The buffer is sorted descending across the wave; with the list
+// ascending, their lane-wise minimum holds the 64 smallest keys of the
+// union as a bitonic sequence, which six exchange stages sort.
 __device__ __forceinline__ int wave_merge64(uint64_t* L, const Segs& b, int len, int kc, int lane) {
   const int c = b.cnt[0] + b.cnt[1] + b.cnt[2] + b.cnt[3];
   const int sg = lane >> 4, e = lane & 15;
@@ -210,11 +221,8 @@ __device__ __forceinline__ int wave_merge64(uint64_t* L, const Segs& b, int len,
   const int segc = sg == 0 ? b.cnt[0] : sg == 1 ? b.cnt[1] : sg == 2 ? b.cnt[2] : b.cnt[3];
   uint64_t x = e < segc ? segp[e] : kEmptyKey;
   const uint64_t l = lane < len ? L[lane] : kEmptyKey;
-  x = bitonic_sort64(x, lane);
-  const uint32_t rlo = (uint32_t)__shfl((int)(uint32_t)x, 63 - lane);
-  const uint32_t rhi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), 63 - lane);
-  const uint64_t xr = ((uint64_t)rhi << 32) | rlo;
-  uint64_t m = l < xr ? l : xr;
+  x = bitonic_sort64(x, lane, true);
+  uint64_t m = l < x ? l : x;
   m = bitonic_clean64(m, lane);
   wave_sync();
   if (lane < kc) L[lane] = m;

@@ -52,7 +52,10 @@ struct TileCfg {
 
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <int KIND, int NG>
+// SMALL: every instance of the launch has k' <= 64 and the buffer holds 64
+// keys (16 per lane), so every merge is the register bitonic merge and the
+// rank-merge code is not compiled in.
+template <int KIND, int NG, bool SMALL>
 __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
   using Cfg = TileCfg<KIND>;
   constexpr int ES = Cfg::es, G = Cfg::group;
@@ -189,7 +192,11 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
         sg.seg[k] = bufs + (size_t)qs * q_stride + k * seg_stride;
         sg.cnt[k] = __builtin_amdgcn_readlane(lcnt, j + 16 * k);
       }
-      const int nl = wave_merge(lists + (size_t)qs * kc, sg, lens[qs], kc, sub, lane);
+      int nl;
+      if constexpr (SMALL)
+        nl = wave_merge64(lists + (size_t)qs * kc, sg, lens[qs], kc, lane);
+      else
+        nl = wave_merge(lists + (size_t)qs * kc, sg, lens[qs], kc, sub, lane);
       if (lane == 0) lens[qs] = nl;
       wave_sync();
     }
@@ -368,14 +375,14 @@ __host__ __device__ constexpr size_t fused_lds_size(int es, int waves, int kc, i
   return fused_dyn_lds(waves, kc, cb) + 2 * kStepRefs * 4 + 2 * (size_t)kStepRefs * cw * es;
 }
 
-template <int KIND, int NG>
+template <int KIND, int NG, bool SMALL>
 hipError_t launch_fused_one(const FusedParams& p, hipStream_t stream) {
   static bool attr_set = false;
   if (!attr_set) {
     hipFuncAttributes fa;
-    hipError_t e = hipFuncGetAttributes(&fa, (const void*)fused_kernel<KIND, NG>);
+    hipError_t e = hipFuncGetAttributes(&fa, (const void*)fused_kernel<KIND, NG, SMALL>);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)fused_kernel<KIND, NG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void*)fused_kernel<KIND, NG, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsBytes - (int)fa.sharedSizeBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
@@ -385,8 +392,16 @@ hipError_t launch_fused_one(const FusedParams& p, hipStream_t stream) {
   if (p.items && p.nitems <= 0) return hipSuccess;
   dim3 grid = p.items ? dim3((unsigned)p.nitems) : dim3((unsigned)((p.one.n + nq - 1) / nq), (unsigned)p.one.P);
   dim3 block(p.waves * kWaveSize);
-  hipLaunchKernelGGL((fused_kernel<KIND, NG>), grid, block, lds, stream, p);
+  hipLaunchKernelGGL((fused_kernel<KIND, NG, SMALL>), grid, block, lds, stream, p);
   return hipGetLastError();
+}
+
+// launch the instantiation whose chunk width matches p.ng (one of NGS)
+template <int KIND, bool SMALL, int... NGS>
+hipError_t dispatch_ng(const FusedParams& p, hipStream_t stream) {
+  hipError_t r = hipErrorInvalidValue;
+  (void)((p.ng == NGS ? (r = launch_fused_one<KIND, NGS, SMALL>(p, stream), true) : false) || ...);
+  return r;
 }
 
 }  // namespace knn

@@ -141,10 +141,12 @@ hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, cons
 hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* centre, hipStream_t stream);
 size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw);
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream);
-hipError_t launch_fused_f32lo(int ng, const FusedParams& p, hipStream_t stream);
-hipError_t launch_fused_f32hi(int ng, const FusedParams& p, hipStream_t stream);
-hipError_t launch_fused_half(int kind, int ng, const FusedParams& p, hipStream_t stream);
-hipError_t launch_fused_valu(int kind, int ng, const FusedParams& p, hipStream_t stream);
+// one per instantiation unit knn_fused_<kind>_<s|l>.hip (s: k' <= 64 only)
+#define KNN_FUSED_UNIT(name) hipError_t launch_fused_##name(const FusedParams& p, hipStream_t stream);
+KNN_FUSED_UNIT(f32lo_s) KNN_FUSED_UNIT(f32lo_l) KNN_FUSED_UNIT(f32hi_s) KNN_FUSED_UNIT(f32hi_l)
+KNN_FUSED_UNIT(bf16_s) KNN_FUSED_UNIT(bf16_l) KNN_FUSED_UNIT(f16_s) KNN_FUSED_UNIT(f16_l)
+KNN_FUSED_UNIT(l1_s) KNN_FUSED_UNIT(l1_l) KNN_FUSED_UNIT(linf_s) KNN_FUSED_UNIT(linf_l)
+#undef KNN_FUSED_UNIT
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
 size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);

@@ -110,12 +110,15 @@ size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw) {
 }
 
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream) {
+  const bool s = p.kc_max <= 64 && p.cb / 4 <= 16;  // register merge only
   switch (kind) {
-    case TILE_L2_F32: return p.ng <= 8 ? launch_fused_f32lo(p.ng, p, stream) : launch_fused_f32hi(p.ng, p, stream);
-    case TILE_L2_BF16:
-    case TILE_L2_F16: return launch_fused_half(kind, p.ng, p, stream);
-    case TILE_L1_F32:
-    case TILE_LINF_F32: return launch_fused_valu(kind, p.ng, p, stream);
+    case TILE_L2_F32:
+      if (p.ng <= 8) return s ? launch_fused_f32lo_s(p, stream) : launch_fused_f32lo_l(p, stream);
+      return s ? launch_fused_f32hi_s(p, stream) : launch_fused_f32hi_l(p, stream);
+    case TILE_L2_BF16: return s ? launch_fused_bf16_s(p, stream) : launch_fused_bf16_l(p, stream);
+    case TILE_L2_F16: return s ? launch_fused_f16_s(p, stream) : launch_fused_f16_l(p, stream);
+    case TILE_L1_F32: return s ? launch_fused_l1_s(p, stream) : launch_fused_l1_l(p, stream);
+    case TILE_LINF_F32: return s ? launch_fused_linf_s(p, stream) : launch_fused_linf_l(p, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -45,18 +45,22 @@ def gmm_centres(comps: int, d: int, workload_id: int) -> np.ndarray:
 
 
 def gmm(npts: int, d: int, comps: int, sigma: float, workload_id: int, role: int,
-        return_labels: bool = False):
+        return_labels: bool = False, threads: int = 1, centres_id: int | None = None):
     """``npts`` float32 points from the isotropic mixture of workload ``workload_id``.
 
     Points are drawn in blocks of ``GMM_BLOCK`` from per-block streams
     (``SeedSequence([workload_id, role, block])``), so a shorter set is an
     exact prefix of a longer one and a million-point set never needs a float64
-    copy of the whole array.
+    copy of the whole array.  Blocks are independent, so ``threads`` > 1
+    fills them concurrently with identical results.  ``centres_id`` takes the
+    mixture centres of another workload id (several sets of one mixture).
     """
-    centres = gmm_centres(comps, d, workload_id)
+    centres = gmm_centres(comps, d, workload_id if centres_id is None else centres_id)
     out = np.empty((npts, d), dtype=np.float32)
     labels = np.empty(npts, dtype=np.int32) if return_labels else None
-    for b, s in enumerate(range(0, npts, GMM_BLOCK)):
+
+    def fill(b):
+        s = b * GMM_BLOCK
         e = min(npts, s + GMM_BLOCK)
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(workload_id), int(role), b])))
         lab = rng.integers(0, comps, GMM_BLOCK)[: e - s]
@@ -64,6 +68,16 @@ def gmm(npts: int, d: int, comps: int, sigma: float, workload_id: int, role: int
         out[s:e] = (centres[lab] + sigma * noise).astype(np.float32)
         if return_labels:
             labels[s:e] = lab
+
+    nblocks = (npts + GMM_BLOCK - 1) // GMM_BLOCK
+    if threads > 1 and nblocks > 1:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(fill, range(nblocks)))
+    else:
+        for b in range(nblocks):
+            fill(b)
     if return_labels:
         return out, labels
     return out
@@ -92,6 +106,70 @@ WORKLOADS = {
     # precision form: m = 2**20, n = 65536, d = 128, k = 32, 1024 components
     "gmm1m_d128": dict(wid=3, m=1 << 20, n=65536, d=128, k=32, kind="gmm", comps=1024, sigma=0.1),
 }
+
+# batched form: 512 independent instances, uniform [0,1) data
+BATCH512 = dict(wid=7, count=512, m=(1000, 200000), n=(16, 4096), d=(16, 32, 64, 128), k=(1, 8, 32, 100))
+
+# serving form: four resident sets of one 1024-component mixture (sigma 0.1,
+# d = 128) with 1, 2, 3 and 4 Mi points; requests of 1..2048 queries
+# (uniform; log-uniform as a variant), k in {10, 50}, set uniform, Poisson
+# arrivals
+SERVE4 = dict(wid=6, sets=(1 << 20, 2 << 20, 3 << 20, 4 << 20), d=128, comps=1024, sigma=0.1,
+              n=(1, 2048), k=(10, 50), pool=16384)
+
+
+def batch_specs(spec=BATCH512, count: int | None = None):
+    """[(m, n, d, k)] of the batched workload (k <= m always holds: m >= 1000)."""
+    rng = rng_for(spec["wid"], ROLE_EXTRA)
+    cnt = spec["count"] if count is None else count
+    out = []
+    for _ in range(cnt):
+        m = int(rng.integers(spec["m"][0], spec["m"][1] + 1))
+        n = int(rng.integers(spec["n"][0], spec["n"][1] + 1))
+        d = int(rng.choice(spec["d"]))
+        k = int(rng.choice(spec["k"]))
+        out.append((m, n, d, min(k, m)))
+    return out
+
+
+def batch_instance(i: int, m: int, n: int, d: int, spec=BATCH512):
+    """(R, Q) of instance ``i`` of the batched workload."""
+    R = rng_for(spec["wid"] * 100000 + i, ROLE_REFS).random((m, d), dtype=np.float32)
+    Q = rng_for(spec["wid"] * 100000 + i, ROLE_QUERIES).random((n, d), dtype=np.float32)
+    return R, Q
+
+
+def serve_set(j: int, spec=SERVE4, m: int | None = None, threads: int = 1) -> np.ndarray:
+    """Reference set ``j`` of the serving workload (a prefix of ``m`` rows if given)."""
+    mm = spec["sets"][j] if m is None else m
+    return gmm(mm, spec["d"], spec["comps"], spec["sigma"], spec["wid"] * 100 + j, ROLE_REFS, threads=threads,
+               centres_id=spec["wid"])
+
+
+def serve_queries(j: int, spec=SERVE4, count: int | None = None) -> np.ndarray:
+    """Query pool of set ``j``: points of the same mixture, another stream."""
+    return gmm(spec["pool"] if count is None else count, spec["d"], spec["comps"], spec["sigma"],
+               spec["wid"] * 100 + j, ROLE_QUERIES, centres_id=spec["wid"])
+
+
+def serve_requests(count: int, spec=SERVE4, seed_role: int = ROLE_REQUESTS, sizes: str = "uniform"):
+    """[(gap, set, offset, n, k)]: exponential gaps of unit mean (scale by 1/rate),
+    set index, offset into that set's query pool, size and k.  ``sizes`` is
+    "uniform" (n uniform in the range) or "loguniform"."""
+    rng = rng_for(spec["wid"], seed_role)
+    lo, hi = spec["n"]
+    out = []
+    for _ in range(count):
+        gap = float(rng.exponential(1.0))
+        s = int(rng.integers(len(spec["sets"])))
+        if sizes == "uniform":
+            n = int(rng.integers(lo, hi + 1))
+        else:
+            n = int(min(hi, max(lo, np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi + 1)))))))
+        off = int(rng.integers(0, spec["pool"] - n + 1))
+        k = int(rng.choice(spec["k"]))
+        out.append((gap, s, off, n, k))
+    return out
 
 
 def workload(name: str, n: int | None = None, m: int | None = None):
