@@ -61,11 +61,29 @@ def kernel_roofline(name: str, avg_s: float, pairs: float, d: float):
         peak = PEAK_FP32_MFMA_TFLOPS if name.endswith("f32") else PEAK_BF16_MFMA_TFLOPS
         ach = flops / avg_s / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": None, "kernel": name, "avg_ms": avg_s * 1e3, "work_per_launch": flops}
+                "traffic": None, "traffic_unit": "HBM bytes per launch", "kernel": name, "avg_ms": avg_s * 1e3,
+                "work_per_launch": flops}
     ops = 2.0 * d * pairs  # one subtract + one absolute accumulate (sum or max) per pair and dimension
     ach = ops / avg_s / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TOPS,
-            "traffic": None, "kernel": name, "avg_ms": avg_s * 1e3, "work_per_launch": ops}
+            "traffic": None, "traffic_unit": "HBM bytes per launch", "kernel": name, "avg_ms": avg_s * 1e3,
+            "work_per_launch": ops}
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the fused kernels from the committed counter
+    summary, or {} when the kernel sources have changed since it was taken."""
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", f"fused_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return {}
+    info = json.load(open(path))
+    h = hashlib.sha1(b"".join(open(os.path.join(root, f), "rb").read() for f in info["source_files"])).hexdigest()
+    if h[:16] != info["source_hash"]:
+        return {}
+    return {name: v["read"] + v["write"] for name, v in info["per_launch_bytes"].items()}
 
 
 def host_threads() -> int:
@@ -109,7 +127,7 @@ def oracle_sample(Q, R, k, metrics, target_s, seed=12345, max_rows=None):
     threads = host_threads()
     n = Q.shape[0]
     rng = np.random.default_rng(seed)
-    probe = rng.choice(n, size=min(n, 16), replace=False)
+    probe = rng.choice(n, size=min(n, 256), replace=False)
     tp = time.perf_counter()
     for mt in metrics:
         oracle.knn(Q[probe], R, k, mt, threads=threads)
@@ -161,6 +179,9 @@ def bench_pairs(args):
         log(f"[bench]   {name:16s} avg {v['avg_ms']:.4f} ms x {v['launches']}")
     rooflines = {name: kernel_roofline(name, v["avg_ms"] / 1e3, float(n) * m, d)
                  for name, v in kernels.items() if name.startswith("fused_")}
+    traffic = measured_traffic(args.workload)
+    for name, roof in rooflines.items():
+        roof["traffic"] = traffic.get(name)
     dominant = max(rooflines, key=lambda nm: kernels[nm]["total_ms"])
 
     result = {
