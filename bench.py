@@ -528,7 +528,9 @@ def bench_serve(args):
             nn = min(n, 4)
             Q = pools[s][off:off + nn]
             dist, idx, _ = srv.wait(srv.submit(s, Q, k))
-            R = synthdata.serve_set(s, spec, threads=th)
+            # the sets are stored in float16 and those rounded rows are canonical:
+            # the oracle sees the same rows, rounded to nearest even
+            R = synthdata.serve_set(s, spec, threads=th).astype(np.float16).astype(np.float32)
             rep = compare(Q, R, k, "l2", dist, idx, tol=1e-5, ref=oracle.knn(Q, R, k, "l2", threads=th))
             recalls.append(rep["recall"])
             worst = max(worst, rep["max_rel_err_hits"])

@@ -173,6 +173,8 @@ struct Plan {
   int kc = 0;
   int dp = 0;
   int es = 4;
+  bool wide = false;  // the 16-bit kernel with 32x32 tiles and register lists
+  int nq = 128;       // queries per workgroup
 };
 
 bool is_half_kind(int kind) { return kind == TILE_L2_BF16 || kind == TILE_L2_F16; }
@@ -214,6 +216,28 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   const int total = p.dp / p.group;
   const int gmax = kind == TILE_L2_F32 ? kMaxGroupsF32 : is_half_kind(kind) ? kMaxGroups16 : kMaxGroupsValu;
   const int ew = env_int("KNN_FUSED_WAVES"), ecb = env_int("KNN_FUSED_CB"), eng = env_int("KNN_FUSED_NG");
+  // 16-bit Euclidean with k' <= 64 and d <= 128: the 32x32-tile kernel with
+  // register lists (KNN_FUSED_WIDE=0 selects the general kernel instead)
+  const char* ewide = getenv("KNN_FUSED_WIDE");
+  if (is_half_kind(kind) && kc <= kWideMaxKc && p.dp <= kWideMaxDp && !(ewide && atoi(ewide) == 0)) {
+    p.wide = true;
+    p.waves = 8;
+    p.cb = 32;
+    p.ng = p.dp / 16;
+    p.nchunk = 1;
+    p.nq = kWideQueries;
+    const int64_t nqb = ceil_div(n, (int64_t)p.nq);
+    int64_t P = ceil_div((int64_t)device_cu_count(), nqb);
+    const int64_t pmax_keys = kFinalMaxKeys / kc;
+    const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
+    P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)32, pmax_keys, pmax_len}));
+    const int ep = env_int("KNN_FUSED_P");
+    if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
+    p.slice_len = round_up(ceil_div(m, P), kStepRefs);
+    p.P = (int)ceil_div(m, p.slice_len);
+    *out = p;
+    return KNN_OK;
+  }
   bool found = false;
   // prefer 8 waves (two per SIMD), then the widest chunk, then the largest
   // candidate buffer (the buffer must hold one step: cb >= 64)
@@ -239,9 +263,10 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   if (!found)
     return fail(KNN_ERR_UNSUPPORTED, "k' = %d candidates per query do not fit the fused kernel's LDS budget", kc);
   p.nchunk = (int)ceil_div(total, p.ng);
+  p.nq = p.waves * kQueriesPerWave;
   const size_t lds = fused_lds_bytes(kind, p.waves, kc, p.cb, p.ng * p.group);
   const int wg_per_cu = std::max<int>(1, (int)(kLdsBytes / lds));
-  const int64_t nqb = ceil_div(n, (int64_t)p.waves * kQueriesPerWave);
+  const int64_t nqb = ceil_div(n, (int64_t)p.nq);
   const int64_t target = (int64_t)device_cu_count() * wg_per_cu;
   int64_t P = ceil_div(target, nqb);
   const int64_t pmax_keys = kFinalMaxKeys / kc;
@@ -356,6 +381,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   fp.cb = plan.cb;
   fp.waves = plan.waves;
   fp.kc_max = plan.kc;
+  fp.wide = plan.wide ? 1 : 0;
   {
     TimedLaunch tl(fused_name(a.kind), a.stream);
     HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");
@@ -653,9 +679,21 @@ struct BatchGroup {
   bool tuned = false;
 };
 
-// candidate (waves, cb) launch configurations of a group, best first
+// A launch configuration is (waves, cb) of the general kernel, or
+// (8, kWideCb) for the 16-bit kernel with 32x32 tiles and register lists.
+constexpr int kWideCb = 0;
+
+bool group_wide_ok(const BatchGroup& g) {
+  return is_half_kind(g.kind) && g.kc_max <= kWideMaxKc && g.dp <= kWideMaxDp;
+}
+
+// queries per workgroup of a configuration
+int config_nq(int waves, int cb) { return cb == kWideCb ? kWideQueries : waves * kQueriesPerWave; }
+
+// candidate launch configurations of a group, best first
 std::vector<std::pair<int, int>> group_configs(const BatchGroup& g) {
   std::vector<std::pair<int, int>> out;
+  if (group_wide_ok(g)) out.push_back({8, kWideCb});
   const int group = group_dims(g.kind);
   for (int waves : {8, 4, 2}) {
     for (int cb : {64, 96, 128}) {
@@ -681,7 +719,7 @@ std::string tune_key(const BatchGroup& g, int64_t pairs) {
     ++bucket;
   }
   char buf[96];
-  snprintf(buf, sizeof buf, "k%d/d%d/c%d/s%d", g.kind, g.dp, g.kclass, bucket);
+  snprintf(buf, sizeof buf, "v2/k%d/d%d/c%d/s%d", g.kind, g.dp, g.kclass, bucket);
   return buf;
 }
 
@@ -730,14 +768,14 @@ namespace knn::host {
 
 bool valid_batch(knn_batch_t b) { return b && b->magic == 0x6b6e6e42u; }
 
-// items of group g for `waves` waves per workgroup, longest first
-std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, int waves) {
+// items of group g for a launch configuration, longest first
+std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, int waves, int cb) {
   struct Cost {
     int64_t cost;
     FusedItem it;
   };
   std::vector<Cost> all;
-  const int nq = waves * kQueriesPerWave;
+  const int nq = config_nq(waves, cb);
   for (size_t j = 0; j < g.insts.size(); ++j) {
     const BatchInst& in = b.inst[g.insts[j]];
     const int64_t qb = ceil_div(in.prob.n, nq);
@@ -776,15 +814,16 @@ FusedParams group_params(knn_batch_s& b, const BatchGroup& g, int waves, int cb,
   fp.insts = (const FusedInst*)(w + g.insts_off);
   fp.items = (const FusedItem*)(w + g.items_off);
   fp.nitems = nitems;
-  fp.ng = g.ng;
-  fp.cb = cb;
+  fp.wide = cb == kWideCb ? 1 : 0;
+  fp.ng = fp.wide ? g.dp / 16 : g.ng;
+  fp.cb = fp.wide ? 32 : cb;
   fp.waves = waves;
   fp.kc_max = g.kc_max;
   return fp;
 }
 
 int batch_set_group_config(knn_batch_s& b, BatchGroup& g, int waves, int cb) {
-  std::vector<FusedItem> items = group_items(b, g, waves);
+  std::vector<FusedItem> items = group_items(b, g, waves, cb);
   int st = upload((unsigned char*)b.ws + g.items_off, items.data(), items.size() * sizeof(FusedItem));
   if (st != KNN_OK) return st;
   g.waves = waves;
@@ -941,23 +980,26 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     const int group = group_dims(g.kind);
     const int total = g.dp / group;
     const int gmax = g.kind == TILE_L2_F32 ? kMaxGroupsF32 : is_half_kind(g.kind) ? kMaxGroups16 : kMaxGroupsValu;
-    bool found = false;
-    for (int ng = std::min(total, gmax); ng >= 1 && !found; --ng) {
+    // the widest chunk at which the general kernel fits; the default
+    // configuration is the first candidate (the 32x32-tile kernel where it
+    // applies)
+    bool general = false;
+    for (int ng = std::min(total, gmax); ng >= 1 && !general; --ng) {
       g.ng = ng;
-      auto cfgs = group_configs(g);
-      if (!cfgs.empty()) {
-        g.waves = cfgs[0].first;
-        g.cb = cfgs[0].second;
-        found = true;
-      }
+      for (auto cfg : group_configs(g)) general = general || cfg.second != kWideCb;
     }
-    if (!found)
+    const auto cfgs = group_configs(g);
+    if (cfgs.empty())
       return fail(KNN_ERR_UNSUPPORTED, "k' = %d candidates per query do not fit the fused kernel's LDS budget",
                   g.kc_max);
+    g.waves = cfgs[0].first;
+    g.cb = cfgs[0].second;
     g.nchunk = (int)ceil_div(total, g.ng);
     // slice length: about four items per workgroup slot of the whole device
-    const int nq = g.waves * kQueriesPerWave;
-    const size_t lds = fused_lds_bytes(g.kind, g.waves, g.kc_max, g.cb, g.ng * group);
+    // (for the default configuration: the first of group_configs)
+    const int nq = config_nq(g.waves, g.cb);
+    const size_t lds =
+        g.cb == kWideCb ? kWideLdsBytes : fused_lds_bytes(g.kind, g.waves, g.kc_max, g.cb, g.ng * group);
     const int64_t slots = (int64_t)cus * std::max<int>(1, (int)(kLdsBytes / lds));
     int64_t blockrefs = 0;
     for (int j : g.insts) blockrefs += ceil_div(b->inst[j].prob.n, nq) * b->inst[j].prob.refs->m;
@@ -986,7 +1028,7 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
   for (BatchGroup& g : b->groups) {
     g.insts_off = take(g.insts.size() * sizeof(FusedInst));
     size_t most = 0;
-    for (int waves : {8, 4, 2}) most = std::max(most, group_items(*b, g, waves).size());
+    for (auto cfg : group_configs(g)) most = std::max(most, group_items(*b, g, cfg.first, cfg.second).size());
     g.items_off = take(most * sizeof(FusedItem));
   }
   b->jobs_off = take(b->inst.size() * sizeof(PrepJob));

@@ -43,6 +43,27 @@ __device__ __forceinline__ float f16_to_f32(uint16_t b) { return (float)__builti
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Wait until at most N vector memory operations of this wave are
+// outstanding (the asynchronous global-to-LDS tile copies included).  The
+// builtin, unlike inline assembly, is visible to the compiler's own wait
+// tracking, which then knows which copies have landed.  gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their
+// maxima.
+template <int N>
+__device__ __forceinline__ void wait_vmem_n() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+__device__ __forceinline__ void wait_vmem() { wait_vmem_n<0>(); }
+
+// Workgroup barrier without the fence of __syncthreads, which would also
+// wait for this wave's outstanding global-to-LDS copies: used where copies
+// for later steps are meant to stay in flight across the barrier (each wave
+// waits for the copies it needs with an explicit vmcnt first).
+__device__ __forceinline__ void barrier_keep_copies() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // compiler and LDS ordering point inside one wave
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

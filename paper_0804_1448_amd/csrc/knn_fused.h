@@ -50,8 +50,6 @@ struct TileCfg {
   static constexpr int group = half16 ? 32 : 16;  // dims per k group
 };
 
-__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
 // SMALL: every instance of the launch has k' <= 64 and the buffer holds 64
 // keys (16 per lane), so every merge is the register bitonic merge and the
 // rank-merge code is not compiled in.

@@ -1,0 +1,276 @@
+// knn_fused16.h -- fused distance + per-query top-k' kernel for the 16-bit
+// Euclidean tiles (bfloat16 / float16 operands, float32 accumulation) with
+// k' <= 64 and at most 128 dimensions: the low-precision form of the
+// brute force of Section 2.1, whose k' candidates are re-ranked exactly in
+// float32 by the finalize kernel.
+//
+// It differs from the general kernel of knn_fused.h in three ways, all for
+// matrix-core throughput:
+//  * 32x32x16 MFMA tiles: a wave scores 32 queries (one output column each)
+//    against 32 references per instruction, so every reference fragment read
+//    from LDS feeds twice as many products as a 16x16 tile;
+//  * the sorted k'-lists live in registers, one key per lane and one
+//    register pair per query (64 registers for 32 queries); only the
+//    candidate buffers stay in LDS, which leaves room for
+//  * three reference tiles in flight: the copy of step s + 2 is issued while
+//    step s is scored, so the copy latency is covered by two steps of work.
+//
+// Lane l of a wave owns query 32 * wave + l % 32 and, in each 32x32 output
+// tile, the 16 rows 8 * (r / 4) + 4 * (l / 32) + r % 4 (r = 0..15); the two
+// lanes of a query each keep a segment of 16 candidate keys.  Scores, keys
+// and the (score, index) order are those of knn_fused.h.
+#pragma once
+
+#include "knn_device.h"
+
+namespace knn {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
+
+constexpr int kF16Waves = 8;
+constexpr int kF16QueriesPerWave = 32;
+constexpr int kF16Queries = kF16Waves * kF16QueriesPerWave;  // queries per workgroup
+static_assert(kF16Queries == kWideQueries, "host and kernel agree on the query block");
+constexpr int kF16Sub = 16;                                  // keys per lane segment
+constexpr int kF16SegStride = kF16Sub + 1;                   // padded against bank conflicts
+constexpr int kF16MaxKeys = 64;                              // list capacity: one key per lane
+
+// NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG, even).
+template <int KIND, int NKG>
+__global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
+  static_assert(KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "16-bit Euclidean tiles only");
+  static_assert(NKG >= 2 && NKG <= 8 && NKG % 2 == 0, "dp = 32, 64, 96 or 128");
+  constexpr int VPR = 2 * NKG;                       // 16-byte slots per staged row
+  constexpr int TILE_BYTES = kStepRefs * VPR * 16;   // 64 references
+  constexpr int NI = kStepRefs * VPR / 64;           // wave-wide copy instructions per tile
+  constexpr int PER_WAVE = (NI + kF16Waves - 1) / kF16Waves;
+  constexpr int SWZ = VPR % 8 == 0 ? 7 : 3;          // slot swizzle (keeps slots below VPR)
+  constexpr int VM_PER_STAGE = PER_WAVE + 1;         // tile slots + norms, per wave
+
+  __shared__ __align__(16) unsigned char tile0[TILE_BYTES], tile1[TILE_BYTES], tile2[TILE_BYTES];
+  __shared__ __align__(16) float norm0[kStepRefs], norm1[kStepRefs], norm2[kStepRefs];
+  __shared__ __align__(16) uint64_t bufs[kF16Waves * 64 * kF16SegStride];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, c = lane & 31, h = lane >> 5;
+  int qblock = blockIdx.x, slice = blockIdx.y;
+  FusedInst in;
+  if (p.items) {
+    const FusedItem it = p.items[blockIdx.x];
+    in = p.insts[it.inst];
+    qblock = it.qblock;
+    slice = it.slice;
+  } else {
+    in = p.one;
+  }
+  const int64_t q0 = (int64_t)qblock * kF16Queries + wave * kF16QueriesPerWave;
+  const int64_t qrow = q0 + c;
+  const int64_t qsafe = qrow < in.n ? qrow : in.n - 1;
+  const int64_t s0 = (int64_t)slice * in.slice_len;
+  const int64_t s1 = min(in.m, s0 + in.slice_len);
+  const int nsteps = (int)((s1 - s0 + kStepRefs - 1) / kStepRefs);
+  const int kc = in.kc;
+
+  // ---- query operands: k group g covers dims 16g..16g+15, lane half h
+  // supplies 16g+8h..+7; negated so that the MFMA adds -q.r to |r|^2 / 2
+  uint4 qb[NKG];
+  {
+    const uint16_t* qp = (const uint16_t*)in.Q + qsafe * (int64_t)in.ldq + 8 * h;
+#pragma unroll
+    for (int g = 0; g < NKG; ++g) {
+      const uint4 v = *(const uint4*)(qp + 16 * g);
+      qb[g] = make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+    }
+  }
+
+  // ---- asynchronous global-to-LDS copies, written as assembly so that the
+  // compiler's wait tracking (which cannot always tell the three tile buffers
+  // apart) does not add full waits before reads of the other buffers.  They
+  // are ordered by the explicit vmcnt waits and the barrier (whose memory
+  // clobber keeps every LDS access on its side).  M0 carries the LDS base of
+  // the wave's 64 destination slots and is restored afterwards.
+  auto copy16 = [](const void* g, void* lds) __attribute__((always_inline)) {
+    const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)lds);  // wave-uniform
+    uint32_t save;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+        : "=&s"(save)
+        : "v"(g), "s"(la));
+  };
+  auto copy4 = [](const void* g, void* lds) __attribute__((always_inline)) {
+    const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)lds);  // wave-uniform
+    uint32_t save;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+        : "=&s"(save)
+        : "v"(g), "s"(la));
+  };
+
+  // ---- staging of step `st` into (dst, ndst): copy instruction i fills
+  // slots 64i..64i+63; slot (row, logical j) lives at row * VPR + (j ^ (row &
+  // SWZ)).  Every wave issues the same number of copies (instructions past
+  // NI repeat earlier ones, and every wave copies the norms: identical bytes
+  // to identical places), so one immediate vmcnt serves all waves.
+  auto stage = [&](int st, unsigned char* dst, float* ndst) __attribute__((always_inline)) {
+    const int64_t rb = s0 + (int64_t)st * kStepRefs;
+    const int rlast = (int)min((int64_t)kStepRefs, s1 - rb) - 1;
+    const unsigned char* gR = (const unsigned char*)in.R + rb * (int64_t)in.ldr * 2;
+    const int rowbytes = in.ldr * 2;
+#pragma unroll
+    for (int u = 0; u < PER_WAVE; ++u) {
+      const int i = (wave + kF16Waves * u) % NI;
+      const int s = 64 * i + lane;
+      const int row = s / VPR, jp = s - row * VPR;
+      const int j = jp ^ (row & SWZ);
+      copy16(gR + min(row, rlast) * rowbytes + j * 16, dst + i * 1024);
+    }
+    copy4(in.rhalf + rb + min(lane, rlast), ndst);
+  };
+
+  // ---- selection state
+  u32x32 Llo, Lhi;  // list key e of query j: lane e of register pair j
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    Llo[j] = 0xffffffffu;
+    Lhi[j] = 0xffffffffu;
+  }
+  float thr = __builtin_huge_valf();
+  int lcnt = 0;
+  uint64_t* myseg = bufs + (size_t)(wave * 64 + lane) * kF16SegStride;
+  const uint64_t* wbufs = bufs + (size_t)wave * 64 * kF16SegStride;
+
+  // merge the buffers of the queries in `qm` (bit j = query j of the wave)
+  // into their lists; refresh the threshold and count of their two lanes
+  auto merge_queries = [&](uint32_t qm) __attribute__((always_inline)) {
+    wave_sync();
+    while (qm) {
+      const int j = __builtin_ctz(qm);
+      qm &= qm - 1;
+      const int cnt0 = __builtin_amdgcn_readlane(lcnt, j);
+      const int cnt1 = __builtin_amdgcn_readlane(lcnt, j + 32);
+      const int e = lane & 31;
+      const uint64_t* sp = wbufs + (size_t)(j + 32 * h) * kF16SegStride;
+      uint64_t x = e < (h ? cnt1 : cnt0) ? sp[e] : kEmptyKey;
+      const uint64_t l = ((uint64_t)Lhi[j] << 32) | Llo[j];
+      x = bitonic_sort64(x, lane, true);
+      uint64_t m = l < x ? l : x;
+      m = bitonic_clean64(m, lane);
+      Llo[j] = (uint32_t)m;
+      Lhi[j] = (uint32_t)(m >> 32);
+      const uint32_t kth = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), kc - 1);
+      if (c == j) {
+        lcnt = 0;
+        thr = kth == 0xffffffffu ? __builtin_huge_valf() : mono_value(kth);
+      }
+    }
+    wave_sync();
+  };
+
+  f32x16 acc[2];
+
+  // one step: stage step+2, score the 64 references of `rt`, select, then
+  // wait for step+1's copy and synchronize.  Near the end of the slice the
+  // copy repeats the last step into a buffer that no later step reads, so
+  // that every step issues the same copies and waits with one vmcnt.
+  auto run_step = [&](int step, const unsigned char* rt, const float* nrd, unsigned char* wt,
+                      float* nwr) __attribute__((always_inline)) {
+    stage(min(step + 2, nsteps - 1), wt, nwr);
+
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const float4 v = *(const float4*)(nrd + 32 * t + 8 * jj + 4 * h);
+        acc[t][4 * jj + 0] = v.x;
+        acc[t][4 * jj + 1] = v.y;
+        acc[t][4 * jj + 2] = v.z;
+        acc[t][4 * jj + 3] = v.w;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < NKG; ++g) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int row = 32 * t + c;
+        const uint4 a = *(const uint4*)(rt + (row * VPR + ((2 * g + h) ^ (row & SWZ))) * 16);
+        if constexpr (KIND == TILE_L2_BF16)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                           __builtin_bit_cast(bf16x8, qb[g]), acc[t], 0, 0, 0);
+        else
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                          __builtin_bit_cast(f16x8, qb[g]), acc[t], 0, 0, 0);
+      }
+    }
+
+    const int64_t tb = s0 + (int64_t)step * kStepRefs;
+    if (tb + kStepRefs > s1) {  // last, partial step of the slice
+      const int rowlim = (int)(s1 - tb);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (32 * t + 8 * (r >> 2) + 4 * h + (r & 3) >= rowlim) acc[t][r] = __builtin_nanf("");
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      float mn = acc[t][0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) mn = fminf(mn, acc[t][r]);
+      if (ballot(mn <= thr)) {
+        int n = 0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) n += acc[t][r] <= thr ? 1 : 0;
+        const uint64_t ov = ballot(lcnt + n > kF16Sub);
+        const uint32_t qm = (uint32_t)(ov | (ov >> 32));
+        if (qm) merge_queries(qm);
+        const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (acc[t][r] <= thr) {
+            myseg[lcnt] = make_key(acc[t][r], rref + (uint32_t)(8 * (r >> 2) + (r & 3)));
+            ++lcnt;
+          }
+      }
+    }
+    if (step == nsteps - 1) {  // end of the slice: flush
+      const uint64_t pend = ballot(lcnt > 0);
+      merge_queries((uint32_t)(pend | (pend >> 32)));
+    }
+
+    wait_vmem_n<VM_PER_STAGE>();  // step+1's copy has landed; step+2's may still run
+    barrier_keep_copies();
+  };
+
+  if (nsteps > 0) {
+    stage(0, tile0, norm0);
+    stage(min(1, nsteps - 1), tile1, norm1);
+    wait_vmem_n<VM_PER_STAGE>();
+    barrier_keep_copies();
+  }
+  for (int step = 0; step < nsteps; step += 3) {
+    run_step(step, tile0, norm0, tile2, norm2);
+    if (step + 1 < nsteps) run_step(step + 1, tile1, norm1, tile0, norm0);
+    if (step + 2 < nsteps) run_step(step + 2, tile2, norm2, tile1, norm1);
+  }
+  wait_vmem();  // no copy may land after the workgroup's LDS is released
+
+  // ---- write this slice's sorted lists: key e of query j from lane e
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const int64_t qg = q0 + j;
+    if (qg < in.n && lane < kc)
+      in.part[(qg * in.P + slice) * kc + lane] = ((uint64_t)Lhi[j] << 32) | Llo[j];
+  }
+}
+
+template <int KIND, int NKG>
+hipError_t launch_fused16_one(const FusedParams& p, hipStream_t stream) {
+  if (p.items && p.nitems <= 0) return hipSuccess;
+  dim3 grid = p.items ? dim3((unsigned)p.nitems)
+                      : dim3((unsigned)((p.one.n + kF16Queries - 1) / kF16Queries), (unsigned)p.one.P);
+  hipLaunchKernelGGL((fused16_kernel<KIND, NKG>), grid, dim3(kF16Waves * kWaveSize), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace knn

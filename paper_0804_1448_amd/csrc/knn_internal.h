@@ -77,6 +77,7 @@ struct FusedParams {
   int cb;               // candidate buffer capacity per query (4 segments)
   int waves;            // waves per workgroup
   int kc_max;           // largest kc of the launch (sizes the LDS lists)
+  int wide;             // 1: the 16-bit kernel with 32x32 tiles and register lists (ng = dp / 16)
 };
 
 // One instance of the merge + exact re-rank + finalize kernel.
@@ -147,6 +148,13 @@ KNN_FUSED_UNIT(f32lo_s) KNN_FUSED_UNIT(f32lo_l) KNN_FUSED_UNIT(f32hi_s) KNN_FUSE
 KNN_FUSED_UNIT(bf16_s) KNN_FUSED_UNIT(bf16_l) KNN_FUSED_UNIT(f16_s) KNN_FUSED_UNIT(f16_l)
 KNN_FUSED_UNIT(l1_s) KNN_FUSED_UNIT(l1_l) KNN_FUSED_UNIT(linf_s) KNN_FUSED_UNIT(linf_l)
 #undef KNN_FUSED_UNIT
+// 16-bit Euclidean kernel with 32x32 tiles and register-resident lists
+// (k' <= 64, dp <= 128): 8 waves of 32 queries per workgroup
+constexpr int kWideQueries = 256;
+constexpr int kWideMaxKc = 64;
+constexpr int kWideMaxDp = 128;
+constexpr size_t kWideLdsBytes = 120 * 1024;  // static LDS of the widest instantiation, rounded up
+hipError_t launch_fused16(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
 size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);
