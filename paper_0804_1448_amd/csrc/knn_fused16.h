@@ -13,12 +13,15 @@
 //    register pair per query (64 registers for 32 queries); only the
 //    candidate buffers stay in LDS, which leaves room for
 //  * three reference tiles in flight: the copy of step s + 2 is issued while
-//    step s is scored, so the copy latency is covered by two steps of work.
+//    step s is scored, so the copy latency is covered by two steps of work;
+// and the two waves that share a SIMD run their scoring and selection
+// phases in opposite order, so that one wave's selection overlaps the
+// other's matrix instructions.
 //
 // Lane l of a wave owns query 32 * wave + l % 32 and, in each 32x32 output
 // tile, the 16 rows 8 * (r / 4) + 4 * (l / 32) + r % 4 (r = 0..15); the two
-// lanes of a query each keep a segment of 16 candidate keys.  Scores, keys
-// and the (score, index) order are those of knn_fused.h.
+// lanes of a query each keep a segment of up to 24 candidate keys.  Scores,
+// keys and the (score, index) order are those of knn_fused.h.
 #pragma once
 
 #include "knn_device.h"
@@ -32,7 +35,7 @@ constexpr int kF16Waves = 8;
 constexpr int kF16QueriesPerWave = 32;
 constexpr int kF16Queries = kF16Waves * kF16QueriesPerWave;  // queries per workgroup
 static_assert(kF16Queries == kWideQueries, "host and kernel agree on the query block");
-constexpr int kF16Sub = 16;                                  // keys per lane segment
+constexpr int kF16Sub = 24;                                  // keys per lane segment
 constexpr int kF16SegStride = kF16Sub + 1;                   // padded against bank conflicts
 constexpr int kF16MaxKeys = 64;                              // list capacity: one key per lane
 
@@ -41,15 +44,15 @@ template <int KIND, int NKG>
 __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   static_assert(KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "16-bit Euclidean tiles only");
   static_assert(NKG >= 2 && NKG <= 8 && NKG % 2 == 0, "dp = 32, 64, 96 or 128");
-  constexpr int VPR = 2 * NKG;                       // 16-byte slots per staged row
-  constexpr int TILE_BYTES = kStepRefs * VPR * 16;   // 64 references
-  constexpr int NI = kStepRefs * VPR / 64;           // wave-wide copy instructions per tile
+  constexpr int VPR = 2 * NKG;                       // 16-byte slots of a row's data
+  constexpr int RS = VPR + 1;                        // slots per staged row: data + one pad slot
+  constexpr int TILE_BYTES = kStepRefs * RS * 16;    // 64 references
+  constexpr int NI = RS;                             // wave-wide copy instructions per tile
   constexpr int PER_WAVE = (NI + kF16Waves - 1) / kF16Waves;
-  constexpr int SWZ = VPR % 8 == 0 ? 7 : 3;          // slot swizzle (keeps slots below VPR)
   constexpr int VM_PER_STAGE = PER_WAVE + 1;         // tile slots + norms, per wave
 
-  __shared__ __align__(16) unsigned char tile0[TILE_BYTES], tile1[TILE_BYTES], tile2[TILE_BYTES];
-  __shared__ __align__(16) float norm0[kStepRefs], norm1[kStepRefs], norm2[kStepRefs];
+  __shared__ __align__(16) unsigned char tiles[3 * TILE_BYTES];  // three steps in flight
+  __shared__ __align__(16) float norms[3 * kStepRefs];
   __shared__ __align__(16) uint64_t bufs[kF16Waves * 64 * kF16SegStride];
 
   const int tid = threadIdx.x;
@@ -108,10 +111,14 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   };
 
   // ---- staging of step `st` into (dst, ndst): copy instruction i fills
-  // slots 64i..64i+63; slot (row, logical j) lives at row * VPR + (j ^ (row &
-  // SWZ)).  Every wave issues the same number of copies (instructions past
-  // NI repeat earlier ones, and every wave copies the norms: identical bytes
-  // to identical places), so one immediate vmcnt serves all waves.
+  // slots 64i..64i+63; slot j of row r lives at r * RS + j, the pad slot
+  // (j = VPR) repeating the row's last data slot.  With a row stride of an
+  // odd number of 16-byte slots the operand reads of 8 consecutive rows hit
+  // distinct banks, and every (tile, k group) read is a fixed offset from
+  // one per-lane address.  Every wave issues the same number of copies
+  // (instructions past NI repeat earlier ones, and every wave copies the
+  // norms: identical bytes to identical places), so one immediate vmcnt
+  // serves all waves.
   auto stage = [&](int st, unsigned char* dst, float* ndst) __attribute__((always_inline)) {
     const int64_t rb = s0 + (int64_t)st * kStepRefs;
     const int rlast = (int)min((int64_t)kStepRefs, s1 - rb) - 1;
@@ -121,8 +128,8 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
     for (int u = 0; u < PER_WAVE; ++u) {
       const int i = (wave + kF16Waves * u) % NI;
       const int s = 64 * i + lane;
-      const int row = s / VPR, jp = s - row * VPR;
-      const int j = jp ^ (row & SWZ);
+      const int row = s / RS, jp = s - row * RS;
+      const int j = min(jp, VPR - 1);
       copy16(gR + min(row, rlast) * rowbytes + j * 16, dst + i * 1024);
     }
     copy4(in.rhalf + rb + min(lane, rlast), ndst);
@@ -169,14 +176,12 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
 
   f32x16 acc[2];
 
-  // one step: stage step+2, score the 64 references of `rt`, select, then
-  // wait for step+1's copy and synchronize.  Near the end of the slice the
-  // copy repeats the last step into a buffer that no later step reads, so
-  // that every step issues the same copies and waits with one vmcnt.
-  auto run_step = [&](int step, const unsigned char* rt, const float* nrd, unsigned char* wt,
-                      float* nwr) __attribute__((always_inline)) {
-    stage(min(step + 2, nsteps - 1), wt, nwr);
-
+  // ---- scoring phase: the 64 references of step `st` against the wave's
+  // 32 queries, |r|^2 / 2 preloaded into the accumulators
+  auto score = [&](int st) __attribute__((always_inline)) {
+    const int b = st % 3;
+    const unsigned char* rt = tiles + b * TILE_BYTES;
+    const float* nrd = norms + b * kStepRefs;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
 #pragma unroll
@@ -188,12 +193,12 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
         acc[t][4 * jj + 3] = v.w;
       }
     }
+    const unsigned char* ra = rt + (c * RS + h) * 16;
 #pragma unroll
     for (int g = 0; g < NKG; ++g) {
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const int row = 32 * t + c;
-        const uint4 a = *(const uint4*)(rt + (row * VPR + ((2 * g + h) ^ (row & SWZ))) * 16);
+        const uint4 a = *(const uint4*)(ra + (32 * t * RS + 2 * g) * 16);
         if constexpr (KIND == TILE_L2_BF16)
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                            __builtin_bit_cast(bf16x8, qb[g]), acc[t], 0, 0, 0);
@@ -202,26 +207,40 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
                                                           __builtin_bit_cast(f16x8, qb[g]), acc[t], 0, 0, 0);
       }
     }
+    // schedule: the eight norm reads and the first PF operand reads, then
+    // one matrix instruction per further read, so that PF reads are in
+    // flight while each instruction runs
+    constexpr int NA = 2 * NKG, PF = NA < 4 ? NA : 4;
+    __builtin_amdgcn_sched_group_barrier(0x100, 8 + PF, 0);
+#pragma unroll
+    for (int i = 0; i < NA - PF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, PF, 0);
+  };
 
-    const int64_t tb = s0 + (int64_t)step * kStepRefs;
+  // ---- selection phase over the scores of step `st` (in acc).  A lane
+  // holding more than kF16Sub - 16 keys that has a candidate in a tile
+  // first has its query merged, so that the tile's up to 16 keys fit.
+  auto select = [&](int st) __attribute__((always_inline)) {
+    const int64_t tb = s0 + (int64_t)st * kStepRefs;
     if (tb + kStepRefs > s1) {  // last, partial step of the slice
-      const int rowlim = (int)(s1 - tb);
+      const int lim = (int)(s1 - tb) - 4 * h;  // rows of this lane: 32t + 8(r/4) + 4h + r%4
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          if (32 * t + 8 * (r >> 2) + 4 * h + (r & 3) >= rowlim) acc[t][r] = __builtin_nanf("");
+          if (32 * t + 8 * (r >> 2) + (r & 3) >= lim) acc[t][r] = __builtin_nanf("");
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       float mn = acc[t][0];
 #pragma unroll
       for (int r = 1; r < 16; ++r) mn = fminf(mn, acc[t][r]);
-      if (ballot(mn <= thr)) {
-        int n = 0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) n += acc[t][r] <= thr ? 1 : 0;
-        const uint64_t ov = ballot(lcnt + n > kF16Sub);
+      const bool any = mn <= thr;
+      if (ballot(any)) {
+        const uint64_t ov = ballot(any && lcnt > kF16Sub - 16);
         const uint32_t qm = (uint32_t)(ov | (ov >> 32));
         if (qm) merge_queries(qm);
         const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
@@ -233,25 +252,44 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
           }
       }
     }
-    if (step == nsteps - 1) {  // end of the slice: flush
-      const uint64_t pend = ballot(lcnt > 0);
-      merge_queries((uint32_t)(pend | (pend >> 32)));
-    }
-
-    wait_vmem_n<VM_PER_STAGE>();  // step+1's copy has landed; step+2's may still run
-    barrier_keep_copies();
   };
 
+  // ---- step loop.  Waves 0-3 score step s and then select it; waves 4-7
+  // (which share the SIMDs with 0-3) first select step s-1 and then score
+  // step s, so on each SIMD one wave's selection runs beside the other's
+  // matrix instructions.  One extra pass lets waves 4-7 select the last
+  // step.  Each step stages step+2 (near the end of the slice: a repeat of
+  // the last step into a buffer no later step reads, so every step issues
+  // the same copies and waits with one vmcnt), then waits for step+1's copy.
+  const bool lead = wave < kF16Waves / 2;
   if (nsteps > 0) {
-    stage(0, tile0, norm0);
-    stage(min(1, nsteps - 1), tile1, norm1);
+    stage(0, tiles, norms);
+    stage(min(1, nsteps - 1), tiles + TILE_BYTES, norms + kStepRefs);
     wait_vmem_n<VM_PER_STAGE>();
     barrier_keep_copies();
   }
-  for (int step = 0; step < nsteps; step += 3) {
-    run_step(step, tile0, norm0, tile2, norm2);
-    if (step + 1 < nsteps) run_step(step + 1, tile1, norm1, tile0, norm0);
-    if (step + 2 < nsteps) run_step(step + 2, tile2, norm2, tile1, norm1);
+  for (int step = 0; step <= nsteps; ++step) {
+    if (step < nsteps) {
+      const int b = (step + 2) % 3;
+      stage(min(step + 2, nsteps - 1), tiles + b * TILE_BYTES, norms + b * kStepRefs);
+    }
+    if (lead) {
+      if (step < nsteps) {
+        score(step);
+        select(step);
+      }
+    } else {
+      if (step > 0) select(step - 1);
+      if (step < nsteps) score(step);
+    }
+    if (step < nsteps) {
+      wait_vmem_n<VM_PER_STAGE>();  // step+1's copy has landed; step+2's may still run
+      barrier_keep_copies();
+    }
+  }
+  {  // end of the slice: flush every buffer
+    const uint64_t pend = ballot(lcnt > 0);
+    merge_queries((uint32_t)(pend | (pend >> 32)));
   }
   wait_vmem();  // no copy may land after the workgroup's LDS is released
 

@@ -153,7 +153,7 @@ KNN_FUSED_UNIT(l1_s) KNN_FUSED_UNIT(l1_l) KNN_FUSED_UNIT(linf_s) KNN_FUSED_UNIT(
 constexpr int kWideQueries = 256;
 constexpr int kWideMaxKc = 64;
 constexpr int kWideMaxDp = 128;
-constexpr size_t kWideLdsBytes = 120 * 1024;  // static LDS of the widest instantiation, rounded up
+constexpr size_t kWideLdsBytes = 149 * 1024;  // static LDS of the widest instantiation, rounded up
 hipError_t launch_fused16(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
