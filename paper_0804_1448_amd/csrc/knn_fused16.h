@@ -220,9 +220,11 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
     __builtin_amdgcn_sched_group_barrier(0x008, PF, 0);
   };
 
-  // ---- selection phase over the scores of step `st` (in acc).  A lane
-  // holding more than kF16Sub - 16 keys that has a candidate in a tile
-  // first has its query merged, so that the tile's up to 16 keys fit.
+  // ---- selection phase over the scores of step `st` (in acc).  Before a
+  // tile's candidates are appended, a lane whose segment might overflow has
+  // its query merged; the bound on the lane's new keys is 4 per group of 4
+  // scores whose minimum passes the threshold (the group minima also give
+  // the tile minimum that decides whether the tile has a candidate at all).
   auto select = [&](int st) __attribute__((always_inline)) {
     const int64_t tb = s0 + (int64_t)st * kStepRefs;
     if (tb + kStepRefs > s1) {  // last, partial step of the slice
@@ -235,12 +237,14 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      float mn = acc[t][0];
+      float mq[4];
 #pragma unroll
-      for (int r = 1; r < 16; ++r) mn = fminf(mn, acc[t][r]);
-      const bool any = mn <= thr;
-      if (ballot(any)) {
-        const uint64_t ov = ballot(any && lcnt > kF16Sub - 16);
+      for (int q = 0; q < 4; ++q)
+        mq[q] = fminf(fminf(acc[t][4 * q], acc[t][4 * q + 1]), fminf(acc[t][4 * q + 2], acc[t][4 * q + 3]));
+      const float mn = fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3]));
+      if (ballot(mn <= thr)) {
+        const int bound = 4 * ((mq[0] <= thr) + (mq[1] <= thr) + (mq[2] <= thr) + (mq[3] <= thr));
+        const uint64_t ov = ballot(lcnt + bound > kF16Sub);
         const uint32_t qm = (uint32_t)(ov | (ov >> 32));
         if (qm) merge_queries(qm);
         const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
