@@ -249,11 +249,15 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
         if (qm) merge_queries(qm);
         const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          if (acc[t][r] <= thr) {
-            myseg[lcnt] = make_key(acc[t][r], rref + (uint32_t)(8 * (r >> 2) + (r & 3)));
-            ++lcnt;
-          }
+        for (int q = 0; q < 4; ++q) {
+          if (!ballot(mq[q] <= thr)) continue;  // no candidate in this group anywhere in the wave
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (acc[t][4 * q + i] <= thr) {
+              myseg[lcnt] = make_key(acc[t][4 * q + i], rref + (uint32_t)(8 * q + i));
+              ++lcnt;
+            }
+        }
       }
     }
   };

@@ -168,6 +168,63 @@ __device__ __forceinline__ float exact_distance(const float* q, const void* rm, 
   return (s0 + s1) + (s2 + s3);
 }
 
+// One lane's share of an exact distance: dims first, first + stride, ...
+// in runs of `run` (4 float32 or 8 16-bit values per 16-byte load).  The
+// row is zero-padded to a whole number of runs; query values past d are
+// taken as zero, so padded dims contribute nothing.
+__device__ __forceinline__ float exact_distance_run(const float* q, bool qvec, const void* rm, int type, int64_t roff,
+                                                    int d, int metric, int first, int stride, int run) {
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  auto acc4 = [&](float a0, float a1, float a2, float a3) __attribute__((always_inline)) {
+    if (metric == 0) {
+      s0 = fmaf(a0, a0, s0); s1 = fmaf(a1, a1, s1); s2 = fmaf(a2, a2, s2); s3 = fmaf(a3, a3, s3);
+    } else if (metric == 1) {
+      s0 += fabsf(a0); s1 += fabsf(a1); s2 += fabsf(a2); s3 += fabsf(a3);
+    } else {
+      s0 = fmaxf(s0, fabsf(a0)); s1 = fmaxf(s1, fabsf(a1)); s2 = fmaxf(s2, fabsf(a2)); s3 = fmaxf(s3, fabsf(a3));
+    }
+  };
+  auto qload4 = [&](int t) __attribute__((always_inline)) {
+    if (qvec && t + 4 <= d) return *(const float4*)(q + t);
+    return make_float4(t < d ? q[t] : 0.f, t + 1 < d ? q[t + 1] : 0.f, t + 2 < d ? q[t + 2] : 0.f,
+                       t + 3 < d ? q[t + 3] : 0.f);
+  };
+  for (int t = first; t < d; t += stride) {
+    if (type == ELEM_F32) {
+      const float4 rv = *(const float4*)((const float*)rm + roff + t);
+      const float4 qv = qload4(t);
+      acc4(qv.x - rv.x, qv.y - rv.y, qv.z - rv.z, qv.w - rv.w);
+    } else {
+      const uint4 rv = *(const uint4*)((const uint16_t*)rm + roff + t);
+      const uint32_t w[4] = {rv.x, rv.y, rv.z, rv.w};
+      float r8[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint16_t lo = (uint16_t)(w[i] & 0xffffu), hi = (uint16_t)(w[i] >> 16);
+        r8[2 * i] = type == ELEM_F16 ? f16_to_f32(lo) : bf16_to_f32(lo);
+        r8[2 * i + 1] = type == ELEM_F16 ? f16_to_f32(hi) : bf16_to_f32(hi);
+      }
+      const float4 qa = qload4(t), qb = qload4(t + 4);
+      acc4(qa.x - r8[0], qa.y - r8[1], qa.z - r8[2], qa.w - r8[3]);
+      acc4(qb.x - r8[4], qb.y - r8[5], qb.z - r8[6], qb.w - r8[7]);
+    }
+  }
+  if (metric == 2) return fmaxf(fmaxf(s0, s1), fmaxf(s2, s3));
+  return (s0 + s1) + (s2 + s3);
+}
+
+// combine the partial results of the 16 lanes of a row (fixed order)
+__device__ __forceinline__ float reduce16(float s, int metric, int lane) {
+#define KNN_STEP(J)                                                        \
+  {                                                                         \
+    const float o = __uint_as_float(xor_lane32<J>(__float_as_uint(s), lane)); \
+    s = metric == 2 ? fmaxf(s, o) : s + o;                                  \
+  }
+  KNN_STEP(8) KNN_STEP(4) KNN_STEP(2) KNN_STEP(1)
+#undef KNN_STEP
+  return s;
+}
+
 __host__ __device__ inline size_t finalize_wave_bytes(int keys_max, int p_max, int kprime_max) {
   return (((size_t)keys_max * 8 + (size_t)p_max * 4 + (size_t)kprime_max * 8) + 15) & ~(size_t)15;
 }
@@ -237,10 +294,32 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
   __builtin_amdgcn_wave_barrier();
 
   const float* qrow = in.Q + q * (int64_t)in.ldq;
-  for (int j = lane; j < nc; j += 64) {
-    const uint32_t r = cand[j];
-    cdist[j] = r < (uint64_t)in.m ? exact_distance(qrow, in.Rm, in.rm_type, (int64_t)r * in.ldr, in.d, in.metric)
-                                 : __builtin_huge_valf();
+  // Rows that allow 16-byte loads are re-ranked by 16 lanes per candidate
+  // (four candidates at a time, each lane a run of 4 or 8 consecutive dims,
+  // the 16 partial results combined by a fixed tree); others one per lane.
+  const bool vec_rows =
+      ((uintptr_t)in.Rm % 16) == 0 && (in.rm_type == ELEM_F32 ? in.ldr % 4 == 0 : in.ldr % 8 == 0);
+  if (vec_rows) {
+    const int sub = lane & 15, grp = lane >> 4;
+    const int run = in.rm_type == ELEM_F32 ? 4 : 8;  // dims per lane and pass
+    const bool qvec = ((uintptr_t)qrow % 16) == 0;
+    for (int j0 = 0; j0 < nc; j0 += 4) {
+      const int j = j0 + grp;
+      const uint32_t r = j < nc ? cand[j] : 0u;
+      const bool live = j < nc && r < (uint64_t)in.m;
+      float s = 0.f;
+      if (live) s = exact_distance_run(qrow, qvec, in.Rm, in.rm_type, (int64_t)r * in.ldr, in.d, in.metric,
+                                       run * sub, run * 16, run);
+      s = reduce16(s, in.metric, lane);
+      if (sub == 0 && j < nc) cdist[j] = live ? s : __builtin_huge_valf();
+    }
+  } else {
+    for (int j = lane; j < nc; j += 64) {
+      const uint32_t r = cand[j];
+      cdist[j] = r < (uint64_t)in.m
+                     ? exact_distance(qrow, in.Rm, in.rm_type, (int64_t)r * in.ldr, in.d, in.metric)
+                     : __builtin_huge_valf();
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
