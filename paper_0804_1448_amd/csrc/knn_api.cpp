@@ -216,10 +216,10 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   const int total = p.dp / p.group;
   const int gmax = kind == TILE_L2_F32 ? kMaxGroupsF32 : is_half_kind(kind) ? kMaxGroups16 : kMaxGroupsValu;
   const int ew = env_int("KNN_FUSED_WAVES"), ecb = env_int("KNN_FUSED_CB"), eng = env_int("KNN_FUSED_NG");
-  // 16-bit Euclidean with k' <= 64 and d <= 128: the 32x32-tile kernel with
+  // Euclidean with k' <= 64 and d <= 128: the 32x32-tile kernel with
   // register lists (KNN_FUSED_WIDE=0 selects the general kernel instead)
   const char* ewide = getenv("KNN_FUSED_WIDE");
-  if (is_half_kind(kind) && kc <= kWideMaxKc && p.dp <= kWideMaxDp && !(ewide && atoi(ewide) == 0)) {
+  if (kind <= TILE_L2_F16 && kc <= kWideMaxKc && p.dp <= kWideMaxDp && !(ewide && atoi(ewide) == 0)) {
     p.wide = true;
     p.waves = 8;
     p.cb = 32;
@@ -230,7 +230,7 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
     int64_t P = ceil_div((int64_t)device_cu_count(), nqb);
     const int64_t pmax_keys = kFinalMaxKeys / kc;
     const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
-    P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)32, pmax_keys, pmax_len}));
+    P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
     const int ep = env_int("KNN_FUSED_P");
     if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
     p.slice_len = round_up(ceil_div(m, P), kStepRefs);
@@ -271,7 +271,7 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   int64_t P = ceil_div(target, nqb);
   const int64_t pmax_keys = kFinalMaxKeys / kc;
   const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
-  P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)32, pmax_keys, pmax_len}));
+  P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
   const int ep = env_int("KNN_FUSED_P");
   if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
   p.slice_len = round_up(ceil_div(m, P), kStepRefs);
@@ -684,7 +684,7 @@ struct BatchGroup {
 constexpr int kWideCb = 0;
 
 bool group_wide_ok(const BatchGroup& g) {
-  return is_half_kind(g.kind) && g.kc_max <= kWideMaxKc && g.dp <= kWideMaxDp;
+  return g.kind <= TILE_L2_F16 && g.kc_max <= kWideMaxKc && g.dp <= kWideMaxDp;
 }
 
 // queries per workgroup of a configuration

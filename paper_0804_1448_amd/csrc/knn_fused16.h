@@ -1,27 +1,30 @@
-// knn_fused16.h -- fused distance + per-query top-k' kernel for the 16-bit
-// Euclidean tiles (bfloat16 / float16 operands, float32 accumulation) with
-// k' <= 64 and at most 128 dimensions: the low-precision form of the
-// brute force of Section 2.1, whose k' candidates are re-ranked exactly in
-// float32 by the finalize kernel.
+// knn_fused16.h -- fused distance + per-query top-k' kernel for the
+// Euclidean tiles with k' <= 64 and at most 128 dimensions, on 32x32 MFMA
+// tiles: float32 operands (v_mfma_f32_32x32x2f32) or 16-bit operands
+// (v_mfma_f32_32x32x16_{bf16,f16}), float32 accumulation.  The brute force
+// of Section 2.1; the k' candidates are re-ranked exactly in float32 by the
+// finalize kernel.
 //
 // It differs from the general kernel of knn_fused.h in three ways, all for
 // matrix-core throughput:
-//  * 32x32x16 MFMA tiles: a wave scores 32 queries (one output column each)
+//  * 32x32 MFMA tiles: a wave scores 32 queries (one output column each)
 //    against 32 references per instruction, so every reference fragment read
 //    from LDS feeds twice as many products as a 16x16 tile;
 //  * the sorted k'-lists live in registers, one key per lane and one
 //    register pair per query (64 registers for 32 queries); only the
 //    candidate buffers stay in LDS, which leaves room for
-//  * three reference tiles in flight: the copy of step s + 2 is issued while
-//    step s is scored, so the copy latency is covered by two steps of work;
+//  * more reference tiles in flight: with 16-bit tiles (short steps) the
+//    copy of step s + 2 is issued while step s is scored; float32 steps are
+//    long enough for one step of lookahead;
 // and the two waves that share a SIMD run their scoring and selection
 // phases in opposite order, so that one wave's selection overlaps the
 // other's matrix instructions.
 //
 // Lane l of a wave owns query 32 * wave + l % 32 and, in each 32x32 output
 // tile, the 16 rows 8 * (r / 4) + 4 * (l / 32) + r % 4 (r = 0..15); the two
-// lanes of a query each keep a segment of up to 24 candidate keys.  Scores,
-// keys and the (score, index) order are those of knn_fused.h.
+// lanes of a query each keep a segment of candidate keys (24 with 16-bit
+// tiles, 16 with float32 tiles, whose larger staged rows leave less LDS).
+// Scores, keys and the (score, index) order are those of knn_fused.h.
 #pragma once
 
 #include "knn_device.h"
@@ -35,25 +38,30 @@ constexpr int kF16Waves = 8;
 constexpr int kF16QueriesPerWave = 32;
 constexpr int kF16Queries = kF16Waves * kF16QueriesPerWave;  // queries per workgroup
 static_assert(kF16Queries == kWideQueries, "host and kernel agree on the query block");
-constexpr int kF16Sub = 24;                                  // keys per lane segment
-constexpr int kF16SegStride = kF16Sub + 1;                   // padded against bank conflicts
 constexpr int kF16MaxKeys = 64;                              // list capacity: one key per lane
 
-// NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG, even).
+// NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG; even
+// for the 16-bit kinds, whose rows are padded to 32).
 template <int KIND, int NKG>
 __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
-  static_assert(KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "16-bit Euclidean tiles only");
-  static_assert(NKG >= 2 && NKG <= 8 && NKG % 2 == 0, "dp = 32, 64, 96 or 128");
-  constexpr int VPR = 2 * NKG;                       // 16-byte slots of a row's data
+  static_assert(KIND == TILE_L2_F32 || KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "Euclidean tiles only");
+  constexpr bool F32 = KIND == TILE_L2_F32;
+  static_assert(NKG >= 1 && NKG <= 8 && (F32 || NKG % 2 == 0), "dp <= 128");
+  constexpr int ES = F32 ? 4 : 2;                    // element bytes
+  constexpr int STAGES = F32 ? 2 : 3;                // tiles in flight
+  constexpr int SUB = F32 ? 16 : 24;                 // keys per lane segment
+  constexpr int SEG = SUB + 1;                       // padded against bank conflicts
+  constexpr int VPR = NKG * 16 * ES / 16;            // 16-byte slots of a row's data
+  constexpr int NU = VPR / 2;                        // slot pairs: a lane half reads one slot of each
   constexpr int RS = VPR + 1;                        // slots per staged row: data + one pad slot
   constexpr int TILE_BYTES = kStepRefs * RS * 16;    // 64 references
   constexpr int NI = RS;                             // wave-wide copy instructions per tile
   constexpr int PER_WAVE = (NI + kF16Waves - 1) / kF16Waves;
   constexpr int VM_PER_STAGE = PER_WAVE + 1;         // tile slots + norms, per wave
 
-  __shared__ __align__(16) unsigned char tiles[3 * TILE_BYTES];  // three steps in flight
-  __shared__ __align__(16) float norms[3 * kStepRefs];
-  __shared__ __align__(16) uint64_t bufs[kF16Waves * 64 * kF16SegStride];
+  __shared__ __align__(16) unsigned char tiles[STAGES * TILE_BYTES];
+  __shared__ __align__(16) float norms[STAGES * kStepRefs];
+  __shared__ __align__(16) uint64_t bufs[kF16Waves * 64 * SEG];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, c = lane & 31, h = lane >> 5;
@@ -75,15 +83,19 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   const int nsteps = (int)((s1 - s0 + kStepRefs - 1) / kStepRefs);
   const int kc = in.kc;
 
-  // ---- query operands: k group g covers dims 16g..16g+15, lane half h
-  // supplies 16g+8h..+7; negated so that the MFMA adds -q.r to |r|^2 / 2
-  uint4 qb[NKG];
+  // ---- query operands, negated so that the MFMA adds -q.r to |r|^2 / 2.
+  // Slot pair u of a row holds 16 bytes for each lane half h: 16-bit dims
+  // 16u + 8h..+7 (one 32x32x16 instruction), or float32 dims 8u + 4h..+3
+  // (four 32x32x2 instructions, one per dim of the lane's run).  The staged
+  // reference rows are read with the same mapping.
+  uint4 qv[NU];
   {
-    const uint16_t* qp = (const uint16_t*)in.Q + qsafe * (int64_t)in.ldq + 8 * h;
+    const unsigned char* qp = (const unsigned char*)in.Q + (qsafe * (int64_t)in.ldq) * ES + 16 * h;
 #pragma unroll
-    for (int g = 0; g < NKG; ++g) {
-      const uint4 v = *(const uint4*)(qp + 16 * g);
-      qb[g] = make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+    for (int u = 0; u < NU; ++u) {
+      const uint4 v = *(const uint4*)(qp + 32 * u);
+      const uint32_t sgn = F32 ? 0x80000000u : 0x80008000u;
+      qv[u] = make_uint4(v.x ^ sgn, v.y ^ sgn, v.z ^ sgn, v.w ^ sgn);
     }
   }
 
@@ -122,8 +134,8 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   auto stage = [&](int st, unsigned char* dst, float* ndst) __attribute__((always_inline)) {
     const int64_t rb = s0 + (int64_t)st * kStepRefs;
     const int rlast = (int)min((int64_t)kStepRefs, s1 - rb) - 1;
-    const unsigned char* gR = (const unsigned char*)in.R + rb * (int64_t)in.ldr * 2;
-    const int rowbytes = in.ldr * 2;
+    const unsigned char* gR = (const unsigned char*)in.R + rb * (int64_t)in.ldr * ES;
+    const int rowbytes = in.ldr * ES;
 #pragma unroll
     for (int u = 0; u < PER_WAVE; ++u) {
       const int i = (wave + kF16Waves * u) % NI;
@@ -144,8 +156,8 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   }
   float thr = __builtin_huge_valf();
   int lcnt = 0;
-  uint64_t* myseg = bufs + (size_t)(wave * 64 + lane) * kF16SegStride;
-  const uint64_t* wbufs = bufs + (size_t)wave * 64 * kF16SegStride;
+  uint64_t* myseg = bufs + (size_t)(wave * 64 + lane) * SEG;
+  const uint64_t* wbufs = bufs + (size_t)wave * 64 * SEG;
 
   // merge the buffers of the queries in `qm` (bit j = query j of the wave)
   // into their lists; refresh the threshold and count of their two lanes
@@ -157,7 +169,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
       const int cnt0 = __builtin_amdgcn_readlane(lcnt, j);
       const int cnt1 = __builtin_amdgcn_readlane(lcnt, j + 32);
       const int e = lane & 31;
-      const uint64_t* sp = wbufs + (size_t)(j + 32 * h) * kF16SegStride;
+      const uint64_t* sp = wbufs + (size_t)(j + 32 * h) * SEG;
       uint64_t x = e < (h ? cnt1 : cnt0) ? sp[e] : kEmptyKey;
       const uint64_t l = ((uint64_t)Lhi[j] << 32) | Llo[j];
       x = bitonic_sort64(x, lane, true);
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   // ---- scoring phase: the 64 references of step `st` against the wave's
   // 32 queries, |r|^2 / 2 preloaded into the accumulators
   auto score = [&](int st) __attribute__((always_inline)) {
-    const int b = st % 3;
+    const int b = st % STAGES;
     const unsigned char* rt = tiles + b * TILE_BYTES;
     const float* nrd = norms + b * kStepRefs;
 #pragma unroll
@@ -195,29 +207,35 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
     }
     const unsigned char* ra = rt + (c * RS + h) * 16;
 #pragma unroll
-    for (int g = 0; g < NKG; ++g) {
+    for (int u = 0; u < NU; ++u) {
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const uint4 a = *(const uint4*)(ra + (32 * t * RS + 2 * g) * 16);
-        if constexpr (KIND == TILE_L2_BF16)
+        const uint4 a = *(const uint4*)(ra + (32 * t * RS + 2 * u) * 16);
+        if constexpr (F32) {
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(qv[u].x), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(qv[u].y), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(qv[u].z), acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(qv[u].w), acc[t], 0, 0, 0);
+        } else if constexpr (KIND == TILE_L2_BF16) {
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
-                                                           __builtin_bit_cast(bf16x8, qb[g]), acc[t], 0, 0, 0);
-        else
+                                                           __builtin_bit_cast(bf16x8, qv[u]), acc[t], 0, 0, 0);
+        } else {
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
-                                                          __builtin_bit_cast(f16x8, qb[g]), acc[t], 0, 0, 0);
+                                                          __builtin_bit_cast(f16x8, qv[u]), acc[t], 0, 0, 0);
+        }
       }
     }
     // schedule: the eight norm reads and the first PF operand reads, then
-    // one matrix instruction per further read, so that PF reads are in
-    // flight while each instruction runs
-    constexpr int NA = 2 * NKG, PF = NA < 4 ? NA : 4;
+    // the matrix instructions of one read per further read, so that PF reads
+    // are in flight while the instructions run
+    constexpr int NA = 2 * NU, PF = NA < 4 ? NA : 4, MPR = F32 ? 4 : 1;
     __builtin_amdgcn_sched_group_barrier(0x100, 8 + PF, 0);
 #pragma unroll
     for (int i = 0; i < NA - PF; ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, MPR, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, PF, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, MPR * PF, 0);
   };
 
   // ---- selection phase over the scores of step `st` (in acc).  Before a
@@ -244,7 +262,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
       const float mn = fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3]));
       if (ballot(mn <= thr)) {
         const int bound = 4 * ((mq[0] <= thr) + (mq[1] <= thr) + (mq[2] <= thr) + (mq[3] <= thr));
-        const uint64_t ov = ballot(lcnt + bound > kF16Sub);
+        const uint64_t ov = ballot(lcnt + bound > SUB);
         const uint32_t qm = (uint32_t)(ov | (ov >> 32));
         if (qm) merge_queries(qm);
         const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
@@ -266,20 +284,22 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   // (which share the SIMDs with 0-3) first select step s-1 and then score
   // step s, so on each SIMD one wave's selection runs beside the other's
   // matrix instructions.  One extra pass lets waves 4-7 select the last
-  // step.  Each step stages step+2 (near the end of the slice: a repeat of
-  // the last step into a buffer no later step reads, so every step issues
-  // the same copies and waits with one vmcnt), then waits for step+1's copy.
+  // step.  Each step stages step + STAGES - 1 (near the end of the slice: a
+  // repeat of the last step into a buffer no later step reads, so every
+  // step issues the same copies and waits with one vmcnt), then waits for
+  // step+1's copy.
   const bool lead = wave < kF16Waves / 2;
+  constexpr int VM_AHEAD = VM_PER_STAGE * (STAGES - 2);  // copies that may stay in flight
   if (nsteps > 0) {
-    stage(0, tiles, norms);
-    stage(min(1, nsteps - 1), tiles + TILE_BYTES, norms + kStepRefs);
-    wait_vmem_n<VM_PER_STAGE>();
+#pragma unroll
+    for (int i = 0; i < STAGES - 1; ++i) stage(min(i, nsteps - 1), tiles + i * TILE_BYTES, norms + i * kStepRefs);
+    wait_vmem_n<VM_AHEAD>();
     barrier_keep_copies();
   }
   for (int step = 0; step <= nsteps; ++step) {
     if (step < nsteps) {
-      const int b = (step + 2) % 3;
-      stage(min(step + 2, nsteps - 1), tiles + b * TILE_BYTES, norms + b * kStepRefs);
+      const int b = (step + STAGES - 1) % STAGES;
+      stage(min(step + STAGES - 1, nsteps - 1), tiles + b * TILE_BYTES, norms + b * kStepRefs);
     }
     if (lead) {
       if (step < nsteps) {
@@ -291,7 +311,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
       if (step < nsteps) score(step);
     }
     if (step < nsteps) {
-      wait_vmem_n<VM_PER_STAGE>();  // step+1's copy has landed; step+2's may still run
+      wait_vmem_n<VM_AHEAD>();  // step+1's copy has landed; later ones may still run
       barrier_keep_copies();
     }
   }

@@ -77,7 +77,7 @@ struct FusedParams {
   int cb;               // candidate buffer capacity per query (4 segments)
   int waves;            // waves per workgroup
   int kc_max;           // largest kc of the launch (sizes the LDS lists)
-  int wide;             // 1: the 16-bit kernel with 32x32 tiles and register lists (ng = dp / 16)
+  int wide;             // 1: the 32x32-tile Euclidean kernel with register lists (ng = dp / 16)
 };
 
 // One instance of the merge + exact re-rank + finalize kernel.
@@ -148,8 +148,8 @@ KNN_FUSED_UNIT(f32lo_s) KNN_FUSED_UNIT(f32lo_l) KNN_FUSED_UNIT(f32hi_s) KNN_FUSE
 KNN_FUSED_UNIT(bf16_s) KNN_FUSED_UNIT(bf16_l) KNN_FUSED_UNIT(f16_s) KNN_FUSED_UNIT(f16_l)
 KNN_FUSED_UNIT(l1_s) KNN_FUSED_UNIT(l1_l) KNN_FUSED_UNIT(linf_s) KNN_FUSED_UNIT(linf_l)
 #undef KNN_FUSED_UNIT
-// 16-bit Euclidean kernel with 32x32 tiles and register-resident lists
-// (k' <= 64, dp <= 128): 8 waves of 32 queries per workgroup
+// Euclidean kernel with 32x32 tiles and register-resident lists (k' <= 64,
+// dp <= 128; float32 or 16-bit tiles): 8 waves of 32 queries per workgroup
 constexpr int kWideQueries = 256;
 constexpr int kWideMaxKc = 64;
 constexpr int kWideMaxDp = 128;

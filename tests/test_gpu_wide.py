@@ -132,3 +132,23 @@ def test_wide_and_general_kernels_agree_with_oracle(K):
     # the two kernels sum the 16-bit products in different orders; their
     # results may differ only where the oracle allows it
     assert abs(ra["recall"] - rb["recall"]) <= 0.002
+
+
+@pytest.mark.parametrize("n,m,d,k", [(700, 9000, 96, 20), (257, 4097, 17, 5), (64, 70000, 128, 56), (1, 70, 33, 7)])
+def test_wide_fp32_matches_oracle_and_general(K, n, m, d, k):
+    """Float32 Euclidean through the 32x32-tile kernel (k + 8 <= 64, d <= 128)
+    and through the general kernel: both pass the oracle check."""
+    import torch
+
+    banner(f"wide fp32 n={n} m={m} d={d} k={k}")
+    Q, R = data("gmm", n, m, d, 500 + d + k)
+    Qd, Rd = torch.from_numpy(Q).cuda(), torch.from_numpy(R).cuda()
+    a = [t.cpu().numpy() for t in K.search(Qd, Rd, k, "l2")]
+    os.environ["KNN_FUSED_WIDE"] = "0"
+    try:
+        b = [t.cpu().numpy() for t in K.search(Qd, Rd, k, "l2")]
+    finally:
+        del os.environ["KNN_FUSED_WIDE"]
+    for dist, idx in (a, b):
+        rep = compare(Q, R, k, "l2", dist, idx, tol=TOL)
+        assert rep["ok"], rep
