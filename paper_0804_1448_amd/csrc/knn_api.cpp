@@ -235,8 +235,19 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
     if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
     p.slice_len = round_up(ceil_div(m, P), kStepRefs);
     p.P = (int)ceil_div(m, p.slice_len);
-    *out = p;
-    return KNN_OK;
+    // Float32 steps are long, so the 32x32 kernel pays off only where its
+    // per-query merges (twice the queries per wave of the general kernel)
+    // are spread over a long scan; short slices keep the general kernel.
+    if (!(kind == TILE_L2_F32 && p.slice_len < kWideMinSliceF32)) {
+      *out = p;
+      return KNN_OK;
+    }
+    p = Plan{};
+    p.kind = kind;
+    p.kc = kc;
+    p.group = group_dims(kind);
+    p.dp = padded_dim(kind, d);
+    p.es = 4;
   }
   bool found = false;
   // prefer 8 waves (two per SIMD), then the widest chunk, then the largest
@@ -684,7 +695,7 @@ struct BatchGroup {
 constexpr int kWideCb = 0;
 
 bool group_wide_ok(const BatchGroup& g) {
-  return g.kind <= TILE_L2_F16 && g.kc_max <= kWideMaxKc && g.dp <= kWideMaxDp;
+  return is_half_kind(g.kind) && g.kc_max <= kWideMaxKc && g.dp <= kWideMaxDp;
 }
 
 // queries per workgroup of a configuration

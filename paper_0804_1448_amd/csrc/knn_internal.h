@@ -153,6 +153,7 @@ KNN_FUSED_UNIT(l1_s) KNN_FUSED_UNIT(l1_l) KNN_FUSED_UNIT(linf_s) KNN_FUSED_UNIT(
 constexpr int kWideQueries = 256;
 constexpr int kWideMaxKc = 64;
 constexpr int kWideMaxDp = 128;
+constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice worth the 32x32 kernel
 constexpr size_t kWideLdsBytes = 149 * 1024;  // static LDS of the widest instantiation, rounded up
 hipError_t launch_fused16(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
