@@ -1019,7 +1019,7 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     for (int j : g.insts) {
       BatchInst& in = b->inst[j];
       const int64_t m = in.prob.refs->m;
-      const int64_t pmax = std::max<int64_t>(1, kFinalMaxKeys / in.kc);
+      const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(64, kFinalMaxKeys / in.kc));
       const int64_t P = std::min<int64_t>(pmax, ceil_div(m, slice));
       in.slice_len = round_up(ceil_div(m, P), kStepRefs);
       in.P = (int)ceil_div(m, in.slice_len);

@@ -269,19 +269,9 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
       // reference row (an LDS broadcast).  Row 16t+4kq+i has swizzle i & 3.
       const int ngv = min(NG, (in.dp - c * CW) / G);
       const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq + c * CW;
-      float4 qn[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) qn[j] = *(const float4*)(qp + 4 * j);
       const unsigned char* rrow = rt + (4 * kq) * VPR * 16;
-#pragma unroll 1
-      for (int g = 0; g < ngv; ++g) {
-        float4 qc[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) qc[j] = qn[j];
-        if (g + 1 < ngv) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) qn[j] = *(const float4*)(qp + (g + 1) * 16 + 4 * j);
-        }
+      // one group of 16 dims: query values qq[0..3], reference rows from LDS
+      auto group = [&](int g, const float4* qq) __attribute__((always_inline)) {
         const unsigned char* rg = rrow + g * 64;
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
@@ -290,15 +280,35 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float4 rv = *(const float4*)(rg + ((t * 16 + i) * VPR + (jj ^ (i & 3))) * 16);
-              const float4 qq = qc[jj];
-              const float a0 = fabsf(qq.x - rv.x), a1 = fabsf(qq.y - rv.y);
-              const float a2 = fabsf(qq.z - rv.z), a3 = fabsf(qq.w - rv.w);
+              const float4 q4 = qq[jj];
+              const float a0 = fabsf(q4.x - rv.x), a1 = fabsf(q4.y - rv.y);
+              const float a2 = fabsf(q4.z - rv.z), a3 = fabsf(q4.w - rv.w);
               if constexpr (KIND == TILE_L1_F32)
                 acc[t][i] = (((acc[t][i] + a0) + a1) + a2) + a3;
               else
                 acc[t][i] = fmaxf(fmaxf(acc[t][i], fmaxf(a0, a1)), fmaxf(a2, a3));
             }
           }
+        }
+      };
+      // groups in pairs, the query values of the next group loaded one group
+      // ahead into the other register set (no copies between them)
+      float4 qa[4], qb[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) qa[j] = *(const float4*)(qp + 4 * j);
+#pragma unroll 1
+      for (int g = 0; g < ngv; g += 2) {
+        if (g + 1 < ngv) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) qb[j] = *(const float4*)(qp + (g + 1) * 16 + 4 * j);
+        }
+        group(g, qa);
+        if (g + 1 < ngv) {
+          if (g + 2 < ngv) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qa[j] = *(const float4*)(qp + (g + 2) * 16 + 4 * j);
+          }
+          group(g + 1, qb);
         }
       }
     }

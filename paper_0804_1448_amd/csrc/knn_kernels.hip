@@ -126,9 +126,10 @@ hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream) {
 
 // ------------------------------------------ merge + exact re-rank + output
 //
-// One wave per query.  (1) The P sorted per-slice lists are merged by rank:
-// the key at position i of list p lands at i + sum over the other lists of
-// the number of their keys below it; the first k' are kept.  (2) Each kept
+// One wave per query.  (1) The P sorted per-slice lists are merged: for few
+// lists by rank (the key at position i of list p lands at i + sum over the
+// other lists of the number of their keys below it), for many by a k-way
+// merge over the list heads held one per lane; the first k' are kept.  (2) Each kept
 // candidate's distance is recomputed exactly in float32 in the difference
 // form (sum of squared differences, sum of absolute differences, or the
 // largest absolute difference) from the canonical rows.  (3) Candidates are
@@ -273,22 +274,45 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
   for (int pl = 0; pl < in.P; ++pl) nvalid += lens[pl];
   const int nc = min(in.kprime, nvalid);
 
-  for (int e = lane; e < T; e += 64) {
-    const int pl = e / in.kc, i = e - pl * in.kc;
-    if (i >= lens[pl] || i >= in.kprime) continue;
-    const uint64_t x = keys[e];
-    int rank = i;
-    for (int o = 0; o < in.P && rank < in.kprime; ++o) {
-      if (o == pl) continue;
-      const uint64_t* L = keys + o * in.kc;
-      int lo = 0, hi = lens[o];
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (L[mid] < x) lo = mid + 1; else hi = mid;
+  if (in.P <= 4 || in.P > 64) {
+    // few lists: each key's merged position by binary searches in the others
+    for (int e = lane; e < T; e += 64) {
+      const int pl = e / in.kc, i = e - pl * in.kc;
+      if (i >= lens[pl] || i >= in.kprime) continue;
+      const uint64_t x = keys[e];
+      int rank = i;
+      for (int o = 0; o < in.P && rank < in.kprime; ++o) {
+        if (o == pl) continue;
+        const uint64_t* L = keys + o * in.kc;
+        int lo = 0, hi = lens[o];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (L[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        rank += lo;
       }
-      rank += lo;
+      if (rank < in.kprime) cand[rank] = (uint32_t)x;
     }
-    if (rank < in.kprime) cand[rank] = (uint32_t)x;
+  } else {
+    // many lists (5..64): a k-way merge.  Lane p holds the head of list
+    // p; each round the wave minimum of the heads (keys are distinct) is
+    // the next key in merged order, and its list advances.
+    int hp = 0;
+    uint64_t head = lane < in.P && lens[lane] > 0 ? keys[lane * in.kc] : kEmptyKey;
+    for (int r = 0; r < nc; ++r) {
+      uint64_t mn = head;
+      mn = min(mn, xor_lane64<32>(mn, lane));
+      mn = min(mn, xor_lane64<16>(mn, lane));
+      mn = min(mn, xor_lane64<8>(mn, lane));
+      mn = min(mn, xor_lane64<4>(mn, lane));
+      mn = min(mn, xor_lane64<2>(mn, lane));
+      mn = min(mn, xor_lane64<1>(mn, lane));
+      if (head == mn) {
+        cand[r] = (uint32_t)mn;
+        ++hp;
+        head = hp < lens[lane] ? keys[lane * in.kc + hp] : kEmptyKey;
+      }
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
