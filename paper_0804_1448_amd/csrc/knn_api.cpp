@@ -173,7 +173,8 @@ struct Plan {
   int kc = 0;
   int dp = 0;
   int es = 4;
-  bool wide = false;  // the 16-bit kernel with 32x32 tiles and register lists
+  bool wide = false;  // the 32x32-tile Euclidean kernel with register lists
+  bool lane = false;  // the one-query-per-lane Manhattan / infinity-norm kernel
   int nq = 128;       // queries per workgroup
 };
 
@@ -248,6 +249,40 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
     p.group = group_dims(kind);
     p.dp = padded_dim(kind, d);
     p.es = 4;
+  }
+  // Manhattan / infinity norm with dp <= 128: one query per lane, 64 per
+  // wave, up to 4 waves per workgroup as the LDS lists allow
+  // (KNN_FUSED_LANE=0 selects the general kernel instead)
+  const char* elane = getenv("KNN_FUSED_LANE");
+  if (kind >= TILE_L1_F32 && p.dp <= kLaneMaxDp && !(elane && atoi(elane) == 0)) {
+    int waves = 0;
+    for (int w : {4, 2, 1}) {
+      if (w > 1 && (int64_t)(w / 2) * kWaveSize >= n) continue;  // no wave without a query
+      if (lane_lds(w, kc) <= (size_t)kLdsBytes) {
+        waves = w;
+        break;
+      }
+    }
+    if (waves > 0) {
+      p.lane = true;
+      p.waves = waves;
+      p.ng = p.dp / 16;
+      p.nchunk = 1;
+      p.nq = waves * kWaveSize;
+      // two waves per SIMD at most (register budget), fewer where LDS binds
+      const int wg_per_cu = std::max<int>(1, std::min<int>(8 / waves, (int)(kLdsBytes / lane_lds(waves, kc))));
+      const int64_t nqb = ceil_div(n, (int64_t)p.nq);
+      int64_t P = ceil_div((int64_t)device_cu_count() * wg_per_cu, nqb);
+      const int64_t pmax_keys = kFinalMaxKeys / kc;
+      const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
+      P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
+      const int ep = env_int("KNN_FUSED_P");
+      if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, m});
+      p.slice_len = round_up(ceil_div(m, P), 8);
+      p.P = (int)ceil_div(m, p.slice_len);
+      *out = p;
+      return KNN_OK;
+    }
   }
   bool found = false;
   // prefer 8 waves (two per SIMD), then the widest chunk, then the largest
@@ -393,6 +428,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   fp.waves = plan.waves;
   fp.kc_max = plan.kc;
   fp.wide = plan.wide ? 1 : 0;
+  fp.lane = plan.lane ? 1 : 0;
   {
     TimedLaunch tl(fused_name(a.kind), a.stream);
     HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");

@@ -211,6 +211,41 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
   wait_vmem();
   __syncthreads();
 
+  // ---- selection over the complete tile `tl` held in acc
+  auto select_tile = [&](int tl) __attribute__((always_inline)) {
+    const int64_t tb = s0 + (int64_t)tl * kStepRefs;
+    if (tb + kStepRefs > s1) {  // last, partial step of the slice
+      const int rowlim = (int)(s1 - tb);
+#pragma unroll
+      for (int t = 0; t < kTilesPerStep; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (t * 16 + 4 * kq + i >= rowlim) acc[t][i] = __builtin_nanf("");
+    }
+    float mn = fminf(fminf(acc[0][0], acc[0][1]), fminf(acc[0][2], acc[0][3]));
+#pragma unroll
+    for (int t = 1; t < kTilesPerStep; ++t)
+      mn = fminf(mn, fminf(fminf(acc[t][0], acc[t][1]), fminf(acc[t][2], acc[t][3])));
+    if (ballot(mn <= thr)) {
+      int n = 0;
+#pragma unroll
+      for (int t = 0; t < kTilesPerStep; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) n += acc[t][i] <= thr ? 1 : 0;
+      const uint32_t ovf = query_bits(ballot(lcnt + n > sub));
+      if (ovf) merge_queries(ovf);  // segments that cannot take this step's survivors
+      const uint32_t rref = (uint32_t)(tb + 4 * kq);
+#pragma unroll
+      for (int t = 0; t < kTilesPerStep; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (acc[t][i] <= thr) {
+            myseg[lcnt] = make_key(acc[t][i], rref + (uint32_t)(t * 16 + i));
+            ++lcnt;
+          }
+    }
+  };
+
   int tile = 0, c = 0;
   // one step: stage the next chunk into (wt, nwr), score the chunk held in
   // (rt, nrd), select if the tile is complete, then wait for the copy and
@@ -271,24 +306,31 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
       const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq + c * CW;
       const unsigned char* rrow = rt + (4 * kq) * VPR * 16;
       // one group of 16 dims: query values qq[0..3], reference rows from LDS
+      // The 64 reads of a group (4 dims of one of 16 rows each) go through
+      // a ring of 8 registers, so that 8 are in flight while the vector ALU
+      // works on earlier ones.
       auto group = [&](int g, const float4* qq) __attribute__((always_inline)) {
         const unsigned char* rg = rrow + g * 64;
+        auto rd = [&](int u) __attribute__((always_inline)) {  // u = 16 jj + 4 t + i
+          const int jj = u >> 4, t = (u >> 2) & 3, i = u & 3;
+          return *(const float4*)(rg + ((t * 16 + i) * VPR + (jj ^ (i & 3))) * 16);
+        };
+        constexpr int DEPTH = 8;
+        float4 ring[DEPTH];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
+        for (int u = 0; u < DEPTH; ++u) ring[u] = rd(u);
 #pragma unroll
-          for (int t = 0; t < kTilesPerStep; ++t) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float4 rv = *(const float4*)(rg + ((t * 16 + i) * VPR + (jj ^ (i & 3))) * 16);
-              const float4 q4 = qq[jj];
-              const float a0 = fabsf(q4.x - rv.x), a1 = fabsf(q4.y - rv.y);
-              const float a2 = fabsf(q4.z - rv.z), a3 = fabsf(q4.w - rv.w);
-              if constexpr (KIND == TILE_L1_F32)
-                acc[t][i] = (((acc[t][i] + a0) + a1) + a2) + a3;
-              else
-                acc[t][i] = fmaxf(fmaxf(acc[t][i], fmaxf(a0, a1)), fmaxf(a2, a3));
-            }
-          }
+        for (int u = 0; u < 64; ++u) {
+          const float4 rv = ring[u % DEPTH];
+          if (u + DEPTH < 64) ring[u % DEPTH] = rd(u + DEPTH);
+          const int jj = u >> 4, t = (u >> 2) & 3, i = u & 3;
+          const float4 q4 = qq[jj];
+          const float a0 = fabsf(q4.x - rv.x), a1 = fabsf(q4.y - rv.y);
+          const float a2 = fabsf(q4.z - rv.z), a3 = fabsf(q4.w - rv.w);
+          if constexpr (KIND == TILE_L1_F32)
+            acc[t][i] = (((acc[t][i] + a0) + a1) + a2) + a3;
+          else
+            acc[t][i] = fmaxf(fmaxf(acc[t][i], fmaxf(a0, a1)), fmaxf(a2, a3));
         }
       };
       // groups in pairs, the query values of the next group loaded one group
@@ -314,40 +356,7 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
     }
 
     // ---- selection once the tiles have seen every chunk
-    if (c == in.nchunk - 1) {
-      const int64_t tb = s0 + (int64_t)tile * kStepRefs;
-      if (tb + kStepRefs > s1) {  // last, partial step of the slice
-        const int rowlim = (int)(s1 - tb);
-#pragma unroll
-        for (int t = 0; t < kTilesPerStep; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (t * 16 + 4 * kq + i >= rowlim) acc[t][i] = __builtin_nanf("");
-      }
-      float mn = fminf(fminf(acc[0][0], acc[0][1]), fminf(acc[0][2], acc[0][3]));
-#pragma unroll
-      for (int t = 1; t < kTilesPerStep; ++t)
-        mn = fminf(mn, fminf(fminf(acc[t][0], acc[t][1]), fminf(acc[t][2], acc[t][3])));
-      if (ballot(mn <= thr)) {
-        int n = 0;
-#pragma unroll
-        for (int t = 0; t < kTilesPerStep; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) n += acc[t][i] <= thr ? 1 : 0;
-        const uint32_t ovf = query_bits(ballot(lcnt + n > sub));
-        if (ovf) merge_queries(ovf);  // segments that cannot take this step's survivors
-        const uint32_t rref = (uint32_t)(tb + 4 * kq);
-#pragma unroll
-        for (int t = 0; t < kTilesPerStep; ++t)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (acc[t][i] <= thr) {
-              myseg[lcnt] = make_key(acc[t][i], rref + (uint32_t)(t * 16 + i));
-              ++lcnt;
-            }
-      }
-      if (tile == ntiles - 1) merge_queries(query_bits(ballot(lcnt > 0)));  // end of the slice: flush
-    }
+    if (c == in.nchunk - 1) select_tile(tile);
 
     wait_vmem();
     __syncthreads();
@@ -360,6 +369,7 @@ __global__ __launch_bounds__(512) void fused_kernel(FusedParams p) {
     run_step(step, tile0, norm0, tile1, norm1);
     if (step + 1 < nsteps) run_step(step + 1, tile1, norm1, tile0, norm0);
   }
+  merge_queries(query_bits(ballot(lcnt > 0)));  // end of the slice: flush
 
   // ---- write this slice's sorted lists
   const int tot = kQueriesPerWave * kc;

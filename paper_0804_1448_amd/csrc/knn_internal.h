@@ -78,6 +78,7 @@ struct FusedParams {
   int waves;            // waves per workgroup
   int kc_max;           // largest kc of the launch (sizes the LDS lists)
   int wide;             // 1: the 32x32-tile Euclidean kernel with register lists (ng = dp / 16)
+  int lane;             // 1: the one-query-per-lane vector-ALU kernel (ng = dp / 16, 64 queries per wave)
 };
 
 // One instance of the merge + exact re-rank + finalize kernel.
@@ -155,7 +156,14 @@ constexpr int kWideMaxKc = 64;
 constexpr int kWideMaxDp = 128;
 constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice worth the 32x32 kernel
 constexpr size_t kWideLdsBytes = 149 * 1024;  // static LDS of the widest instantiation, rounded up
-hipError_t launch_fused16(int kind, const FusedParams& p, hipStream_t stream);
+hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
+// Manhattan / infinity-norm kernel with one query per lane (dp <= 128):
+// `waves` waves of 64 queries per workgroup, each lane with a sorted list of
+// kc keys and a queue of kLaneQueue keys in LDS
+constexpr int kLaneQueue = 8;
+constexpr int kLaneMaxDp = 128;
+hipError_t launch_lane(int kind, const FusedParams& p, hipStream_t stream);
+size_t lane_lds(int waves, int kc);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
 size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);

@@ -1,0 +1,264 @@
+// knn_lane.h -- Manhattan and infinity-norm distances with one query per
+// lane, fused with the per-query top-k' selection.
+//
+// The problem definition of Section 2.1 admits any distance; the Manhattan
+// and infinity-norm distances it names are not contractions, so they run on
+// the vector ALUs in float32.  A wave owns 64 queries, one per lane, and keeps
+// the lane's whole (padded) query row in registers while it walks one slice
+// of the references, NR references per batch.  A reference row is loaded so
+// that lane j of each 16-lane row holds dims 64h + 4j .. 64h + 4j + 3 of the
+// row's 64-dim chunk h (the four rows load the same 256 bytes); the DPP row
+// broadcast (row_newbcast:j) then hands dim 64h + 4j + c to every lane as an
+// operand of the subtraction.  Each query-reference-dimension triple costs
+// one subtraction and one accumulation (|.| is a source modifier), and the
+// distance loop touches no LDS.  Reference rows are loaded one batch ahead.
+//
+// Selection is per lane.  A lane keeps a sorted list of its kc best keys
+// (score, reference index) and a queue of up to kLaneQueue candidates, both
+// in LDS in slot-major order ([slot][lane]: lanes at one slot hit distinct
+// banks), with the list length and queue count in registers.  A score joins
+// the queue if it is <= the list's kc-th score (+inf until the list is full;
+// NaN, used for rows past the end of the slice, never does).  When the
+// queue of some lane might not take the next batch, the wave merges: each
+// lane sorts its queue with a 19-comparator network, finds by binary search
+// along the merge path how many queue keys b belong to the kept
+// min(kc, len + queued) keys, and merges the two sorted runs in place from
+// the back.  The merge also tightens the lane's threshold.
+#pragma once
+
+#include <utility>
+
+#include "knn_device.h"
+
+namespace knn {
+
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {  // lane J of this lane's 16-lane row
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + J, 0xF, 0xF, true));
+}
+
+// 16-byte load through the global address space: the compiler then counts
+// it on vmcnt alone (a flat load also counts on lgkmcnt, which forces a full
+// wait before every LDS access and defeats the one-batch-ahead loads)
+__device__ __forceinline__ float4 gload4(const float* ptr) {
+  const f32x4 v = *(const __attribute__((address_space(1))) f32x4*)ptr;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ float comp(const float4& v, int c) {
+  return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+}
+
+__device__ __forceinline__ void cas64(uint64_t& a, uint64_t& b) {
+  const bool s = a < b;
+  const uint64_t lo = s ? a : b, hi = s ? b : a;
+  a = lo;
+  b = hi;
+}
+
+// ascending sort of 8 keys (Batcher's network, 19 comparators)
+__device__ __forceinline__ void sort8(uint64_t (&x)[8]) {
+  cas64(x[0], x[2]); cas64(x[1], x[3]); cas64(x[4], x[6]); cas64(x[5], x[7]);
+  cas64(x[0], x[4]); cas64(x[1], x[5]); cas64(x[2], x[6]); cas64(x[3], x[7]);
+  cas64(x[0], x[1]); cas64(x[2], x[3]); cas64(x[4], x[5]); cas64(x[6], x[7]);
+  cas64(x[2], x[4]); cas64(x[3], x[5]);
+  cas64(x[1], x[4]); cas64(x[3], x[6]);
+  cas64(x[1], x[2]); cas64(x[3], x[4]); cas64(x[5], x[6]);
+}
+
+// Accumulate dims 64H + 4J .. 64H + 4J + 3 of NR references into acc.
+template <int KIND, int NR, int NCH, int H, int J>
+__device__ __forceinline__ void lane_dims4(float (&acc)[NR], const float4 (&v)[NR][NCH], const float4& q4) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float qd = comp(q4, c);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const float t = fabsf(row_bcast<J>(comp(v[i][H], c)) - qd);
+      if constexpr (KIND == TILE_L1_F32)
+        acc[i] = acc[i] + t;
+      else
+        acc[i] = fmaxf(acc[i], t);
+    }
+  }
+}
+
+template <int KIND, int NR, int NCH, int H, size_t... J>
+__device__ __forceinline__ void lane_chunk(float (&acc)[NR], const float4 (&v)[NR][NCH], const float4* qv,
+                                           std::index_sequence<J...>) {
+  (lane_dims4<KIND, NR, NCH, H, (int)J>(acc, v, qv[16 * H + J]), ...);
+}
+
+template <int KIND, int NR, int NCH, int DP, size_t... H>
+__device__ __forceinline__ void lane_score(float (&acc)[NR], const float4 (&v)[NR][NCH], const float4* qv,
+                                           std::index_sequence<H...>) {
+  (lane_chunk<KIND, NR, NCH, (int)H>(acc, v, qv, std::make_index_sequence<(DP - 64 * (int)H >= 64 ? 16 : (DP - 64 * (int)H) / 4)>{}),
+   ...);
+}
+
+// NG: 16-dim groups of the padded dimension (dp = 16 NG <= 128).
+template <int KIND, int NG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void lane_kernel(FusedParams p) {
+  constexpr int DP = 16 * NG;
+  constexpr int NCH = (DP + 63) / 64;  // 64-dim chunks per row
+  constexpr int NR = 4;                // references per batch
+  constexpr int T = kLaneQueue;
+  static_assert(T == 8, "the queue sort is the 8-key network");
+  static_assert(NR <= T, "a batch must fit an empty queue");
+  extern __shared__ __align__(16) unsigned char smem[];
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  int qblock = blockIdx.x, slice = blockIdx.y;
+  FusedInst in;
+  if (p.items) {
+    const FusedItem it = p.items[blockIdx.x];
+    in = p.insts[it.inst];
+    qblock = it.qblock;
+    slice = it.slice;
+  } else {
+    in = p.one;
+  }
+  const int64_t qrow = ((int64_t)qblock * W + wave) * kWaveSize + lane;
+  const int64_t qsafe = qrow < in.n ? qrow : in.n - 1;
+  const int64_t s0 = (int64_t)slice * in.slice_len;
+  const int64_t s1 = min(in.m, s0 + in.slice_len);
+  const int kc = in.kc;
+  uint64_t* L = (uint64_t*)smem + (size_t)wave * (p.kc_max + T) * kWaveSize + lane;  // L[s * 64]: list slot s
+  uint64_t* X = L + (size_t)p.kc_max * kWaveSize;                                     // X[s * 64]: queue slot s
+
+  // the lane's query row, dims 4g .. 4g + 3 in qv[g]
+  float4 qv[4 * NG];
+  {
+    const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq;
+#pragma unroll
+    for (int g = 0; g < 4 * NG; ++g) qv[g] = gload4(qp + 4 * g);
+  }
+
+  // reference rows r0 .. r0 + NR - 1 (clamped to the slice), lane j of a
+  // 16-lane row holding dims 64h + 4j .. +3 of chunk h; lanes past a short
+  // last chunk repeat its last 16 bytes (never broadcast)
+  const float* Rf = (const float*)in.R;
+  const int jl = lane & 15;
+  auto load = [&](int64_t r0, float4 (&v)[NR][NCH]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int64_t r = min(r0 + i, s1 - 1);
+      const float* row = Rf + r * (int64_t)in.ldr;
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) {
+        constexpr int full = 16;
+        const int nv = (DP - 64 * h) >= 64 ? full : (DP - 64 * h) / 4;
+        const int j = nv < full ? min(jl, nv - 1) : jl;
+        v[i][h] = gload4(row + 64 * h + 4 * j);
+      }
+    }
+  };
+
+  float thr = __builtin_huge_valf();
+  int len = 0, qn = 0;
+
+  // merge every lane's queue into its list (the whole wave takes part)
+  auto merge = [&]() __attribute__((always_inline)) {
+    uint64_t x[T];
+#pragma unroll
+    for (int s = 0; s < T; ++s) x[s] = s < qn ? X[s * kWaveSize] : kEmptyKey;
+    sort8(x);
+#pragma unroll
+    for (int s = 0; s < T; ++s) X[s * kWaveSize] = x[s];
+    const int kp = min(kc, len + qn);
+    // b = number of queue keys among the kp kept: the smallest b in
+    // [lo, hi] whose next queue key does not precede the list key it would
+    // displace
+    int lo = max(0, kp - len), hi = min(qn, kp);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (X[mid * kWaveSize] < L[(kp - mid - 1) * kWaveSize])
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    int b = lo, a = kp - lo, i = kp - 1;
+    // from the back: position i takes the larger of L[a-1] and X[b-1]; once
+    // the queue run is used up the list prefix is already in place
+    while (b > 0) {
+      const uint64_t xq = X[(b - 1) * kWaveSize];
+      const uint64_t xl = a > 0 ? L[(a - 1) * kWaveSize] : 0ull;
+      const bool take_list = a > 0 && xl > xq;
+      L[i * kWaveSize] = take_list ? xl : xq;
+      a -= take_list ? 1 : 0;
+      b -= take_list ? 0 : 1;
+      --i;
+    }
+    len = kp;
+    qn = 0;
+    if (len == kc) thr = mono_value((uint32_t)(L[(kc - 1) * kWaveSize] >> 32));
+  };
+
+  // queue the batch's scores that pass the threshold; merge if the next
+  // batch might not fit some lane's queue
+  auto select = [&](const float (&acc)[NR], int64_t r0) __attribute__((always_inline)) {
+    float sc[NR];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      sc[i] = r0 + i < s1 ? acc[i] : __builtin_nanf("");
+      any |= sc[i] <= thr;
+    }
+    if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (sc[i] <= thr) {
+          X[qn * kWaveSize] = make_key(sc[i], (uint32_t)(r0 + i));
+          ++qn;
+        }
+      if (__builtin_amdgcn_ballot_w64(qn > T - NR)) merge();
+    }
+  };
+
+  float4 va[NR][NCH], vb[NR][NCH];
+  if (s0 < s1) load(s0, va);
+  for (int64_t r0 = s0; r0 < s1; r0 += 2 * NR) {
+    float acc[NR];
+    load(r0 + NR, vb);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) acc[i] = 0.f;
+    lane_score<KIND, NR, NCH, DP>(acc, va, qv, std::make_index_sequence<NCH>{});
+    select(acc, r0);
+    if (r0 + NR >= s1) break;
+    load(r0 + 2 * NR, va);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) acc[i] = 0.f;
+    lane_score<KIND, NR, NCH, DP>(acc, vb, qv, std::make_index_sequence<NCH>{});
+    select(acc, r0 + NR);
+  }
+  if (__builtin_amdgcn_ballot_w64(qn > 0)) merge();
+
+  if (qrow < in.n) {
+    uint64_t* dst = in.part + ((size_t)qrow * in.P + slice) * kc;
+    for (int s = 0; s < kc; ++s) dst[s] = s < len ? L[s * kWaveSize] : kEmptyKey;
+  }
+}
+
+// dynamic LDS of one workgroup of `waves` waves: list and queue slots per lane
+__host__ __device__ constexpr size_t lane_lds_bytes(int waves, int kc_max) {
+  return (size_t)waves * kWaveSize * (size_t)(kc_max + kLaneQueue) * 8;
+}
+
+template <int KIND, int NG>
+hipError_t launch_lane_one(const FusedParams& p, hipStream_t stream) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)lane_kernel<KIND, NG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kLdsBytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (p.items && p.nitems <= 0) return hipSuccess;
+  const int nq = p.waves * kWaveSize;
+  dim3 grid = p.items ? dim3((unsigned)p.nitems) : dim3((unsigned)((p.one.n + nq - 1) / nq), (unsigned)p.one.P);
+  hipLaunchKernelGGL((lane_kernel<KIND, NG>), grid, dim3(p.waves * kWaveSize), lane_lds_bytes(p.waves, p.kc_max),
+                     stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace knn

@@ -1,4 +1,4 @@
-// knn_fused16.h -- fused distance + per-query top-k' kernel for the
+// knn_wide.h -- fused distance + per-query top-k' kernel for the
 // Euclidean tiles with k' <= 64 and at most 128 dimensions, on 32x32 MFMA
 // tiles: float32 operands (v_mfma_f32_32x32x2f32) or 16-bit operands
 // (v_mfma_f32_32x32x16_{bf16,f16}), float32 accumulation.  The brute force
@@ -34,16 +34,16 @@ namespace knn {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
 
-constexpr int kF16Waves = 8;
-constexpr int kF16QueriesPerWave = 32;
-constexpr int kF16Queries = kF16Waves * kF16QueriesPerWave;  // queries per workgroup
-static_assert(kF16Queries == kWideQueries, "host and kernel agree on the query block");
-constexpr int kF16MaxKeys = 64;                              // list capacity: one key per lane
+constexpr int kWideWaves = 8;
+constexpr int kWideQueriesPerWave = 32;
+constexpr int kWideQueriesWG = kWideWaves * kWideQueriesPerWave;  // queries per workgroup
+static_assert(kWideQueriesWG == kWideQueries, "host and kernel agree on the query block");
+constexpr int kWideMaxKeys = 64;                              // list capacity: one key per lane
 
 // NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG; even
 // for the 16-bit kinds, whose rows are padded to 32).
 template <int KIND, int NKG>
-__global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
+__global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
   static_assert(KIND == TILE_L2_F32 || KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "Euclidean tiles only");
   constexpr bool F32 = KIND == TILE_L2_F32;
   static_assert(NKG >= 1 && NKG <= 8 && (F32 || NKG % 2 == 0), "dp <= 128");
@@ -56,12 +56,12 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   constexpr int RS = VPR + 1;                        // slots per staged row: data + one pad slot
   constexpr int TILE_BYTES = kStepRefs * RS * 16;    // 64 references
   constexpr int NI = RS;                             // wave-wide copy instructions per tile
-  constexpr int PER_WAVE = (NI + kF16Waves - 1) / kF16Waves;
+  constexpr int PER_WAVE = (NI + kWideWaves - 1) / kWideWaves;
   constexpr int VM_PER_STAGE = PER_WAVE + 1;         // tile slots + norms, per wave
 
   __shared__ __align__(16) unsigned char tiles[STAGES * TILE_BYTES];
   __shared__ __align__(16) float norms[STAGES * kStepRefs];
-  __shared__ __align__(16) uint64_t bufs[kF16Waves * 64 * SEG];
+  __shared__ __align__(16) uint64_t bufs[kWideWaves * 64 * SEG];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, c = lane & 31, h = lane >> 5;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   } else {
     in = p.one;
   }
-  const int64_t q0 = (int64_t)qblock * kF16Queries + wave * kF16QueriesPerWave;
+  const int64_t q0 = (int64_t)qblock * kWideQueriesWG + wave * kWideQueriesPerWave;
   const int64_t qrow = q0 + c;
   const int64_t qsafe = qrow < in.n ? qrow : in.n - 1;
   const int64_t s0 = (int64_t)slice * in.slice_len;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
     const int rowbytes = in.ldr * ES;
 #pragma unroll
     for (int u = 0; u < PER_WAVE; ++u) {
-      const int i = (wave + kF16Waves * u) % NI;
+      const int i = (wave + kWideWaves * u) % NI;
       const int s = 64 * i + lane;
       const int row = s / RS, jp = s - row * RS;
       const int j = min(jp, VPR - 1);
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
   // repeat of the last step into a buffer no later step reads, so every
   // step issues the same copies and waits with one vmcnt), then waits for
   // step+1's copy.
-  const bool lead = wave < kF16Waves / 2;
+  const bool lead = wave < kWideWaves / 2;
   constexpr int VM_AHEAD = VM_PER_STAGE * (STAGES - 2);  // copies that may stay in flight
   if (nsteps > 0) {
 #pragma unroll
@@ -331,11 +331,11 @@ __global__ __launch_bounds__(512) void fused16_kernel(FusedParams p) {
 }
 
 template <int KIND, int NKG>
-hipError_t launch_fused16_one(const FusedParams& p, hipStream_t stream) {
+hipError_t launch_wide_one(const FusedParams& p, hipStream_t stream) {
   if (p.items && p.nitems <= 0) return hipSuccess;
   dim3 grid = p.items ? dim3((unsigned)p.nitems)
-                      : dim3((unsigned)((p.one.n + kF16Queries - 1) / kF16Queries), (unsigned)p.one.P);
-  hipLaunchKernelGGL((fused16_kernel<KIND, NKG>), grid, dim3(kF16Waves * kWaveSize), 0, stream, p);
+                      : dim3((unsigned)((p.one.n + kWideQueriesWG - 1) / kWideQueriesWG), (unsigned)p.one.P);
+  hipLaunchKernelGGL((wide_kernel<KIND, NKG>), grid, dim3(kWideWaves * kWaveSize), 0, stream, p);
   return hipGetLastError();
 }
 
