@@ -255,22 +255,33 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
   // (KNN_FUSED_LANE=0 selects the general kernel instead)
   const char* elane = getenv("KNN_FUSED_LANE");
   if (kind >= TILE_L1_F32 && p.dp <= kLaneMaxDp && !(elane && atoi(elane) == 0)) {
-    int waves = 0;
-    for (int w : {4, 2, 1}) {
-      if (w > 1 && (int64_t)(w / 2) * kWaveSize >= n) continue;  // no wave without a query
-      if (lane_lds(w, kc) <= (size_t)kLdsBytes) {
-        waves = w;
-        break;
+    // the (waves, queue) pair with the most resident waves per CU (two per
+    // SIMD at most, for registers), the larger queue where it costs none
+    int waves = 0, queue = 0, best = 0;
+    const int eq = env_int("KNN_LANE_QUEUE");
+    for (int t : {12, 8}) {
+      if (eq && t != eq) continue;
+      for (int w : {4, 2, 1}) {
+        if (w > 1 && (int64_t)(w / 2) * kWaveSize >= n) continue;  // no wave without a query
+        const size_t lds = lane_lds(w, kc, t);
+        if (lds > (size_t)kLdsBytes) continue;
+        const int resident = w * std::min<int>(8 / w, (int)(kLdsBytes / lds));
+        if (resident > best) {
+          best = resident;
+          waves = w;
+          queue = t;
+        }
       }
     }
     if (waves > 0) {
       p.lane = true;
       p.waves = waves;
+      p.cb = queue;
       p.ng = p.dp / 16;
       p.nchunk = 1;
       p.nq = waves * kWaveSize;
       // two waves per SIMD at most (register budget), fewer where LDS binds
-      const int wg_per_cu = std::max<int>(1, std::min<int>(8 / waves, (int)(kLdsBytes / lane_lds(waves, kc))));
+      const int wg_per_cu = best / waves;
       const int64_t nqb = ceil_div(n, (int64_t)p.nq);
       int64_t P = ceil_div((int64_t)device_cu_count() * wg_per_cu, nqb);
       const int64_t pmax_keys = kFinalMaxKeys / kc;

@@ -159,11 +159,10 @@ constexpr size_t kWideLdsBytes = 149 * 1024;  // static LDS of the widest instan
 hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
 // Manhattan / infinity-norm kernel with one query per lane (dp <= 128):
 // `waves` waves of 64 queries per workgroup, each lane with a sorted list of
-// kc keys and a queue of kLaneQueue keys in LDS
-constexpr int kLaneQueue = 8;
+// kc keys and a queue of `cb` (8 or 12) keys in LDS
 constexpr int kLaneMaxDp = 128;
 hipError_t launch_lane(int kind, const FusedParams& p, hipStream_t stream);
-size_t lane_lds(int waves, int kc);
+size_t lane_lds(int waves, int kc, int queue);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
 size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);

@@ -14,13 +14,15 @@
 // distance loop touches no LDS.  Reference rows are loaded one batch ahead.
 //
 // Selection is per lane.  A lane keeps a sorted list of its kc best keys
-// (score, reference index) and a queue of up to kLaneQueue candidates, both
+// (score, reference index) and a queue of up to T = 8 or 12 candidates, both
 // in LDS in slot-major order ([slot][lane]: lanes at one slot hit distinct
 // banks), with the list length and queue count in registers.  A score joins
 // the queue if it is <= the list's kc-th score (+inf until the list is full;
-// NaN, used for rows past the end of the slice, never does).  When the
+// NaN, used for rows past the end of the slice, never does).  Distances are
+// non-negative, so scores compare as their bit patterns and a key's
+// monotone code is the pattern with the sign bit set.  When the
 // queue of some lane might not take the next batch, the wave merges: each
-// lane sorts its queue with a 19-comparator network, finds by binary search
+// lane sorts its queue with a comparator network, finds by binary search
 // along the merge path how many queue keys b belong to the kept
 // min(kc, len + queued) keys, and merges the two sorted runs in place from
 // the back.  The merge also tightens the lane's threshold.
@@ -56,14 +58,26 @@ __device__ __forceinline__ void cas64(uint64_t& a, uint64_t& b) {
   b = hi;
 }
 
-// ascending sort of 8 keys (Batcher's network, 19 comparators)
-__device__ __forceinline__ void sort8(uint64_t (&x)[8]) {
-  cas64(x[0], x[2]); cas64(x[1], x[3]); cas64(x[4], x[6]); cas64(x[5], x[7]);
-  cas64(x[0], x[4]); cas64(x[1], x[5]); cas64(x[2], x[6]); cas64(x[3], x[7]);
-  cas64(x[0], x[1]); cas64(x[2], x[3]); cas64(x[4], x[5]); cas64(x[6], x[7]);
-  cas64(x[2], x[4]); cas64(x[3], x[5]);
-  cas64(x[1], x[4]); cas64(x[3], x[6]);
-  cas64(x[1], x[2]); cas64(x[3], x[4]); cas64(x[5], x[6]);
+// Ascending sorts of 8 and 12 keys: Batcher's odd-even merge networks for 8
+// and 16 keys (for 12, the comparators among the first 12 positions: the
+// four missing keys act as +inf, which no comparator moves down).
+constexpr unsigned char kNet8[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                                        {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+constexpr unsigned char kNet12[42][2] = {
+    {0, 1}, {2, 3}, {4, 5}, {6, 7}, {8, 9}, {10, 11}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {8, 10}, {9, 11}, {1, 2}, {5, 6},
+    {9, 10}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4}, {5, 6}, {9, 10}, {0, 8}, {1, 9}, {2, 10},
+    {3, 11}, {4, 8}, {5, 9}, {6, 10}, {7, 11}, {2, 4}, {3, 5}, {6, 8}, {7, 9}, {1, 2}, {3, 4}, {5, 6}, {7, 8}, {9, 10}};
+
+template <int T>
+__device__ __forceinline__ void sort_queue(uint64_t (&x)[T]) {
+  static_assert(T == 8 || T == 12, "queue sizes with a network");
+  if constexpr (T == 8) {
+#pragma unroll
+    for (int c = 0; c < 19; ++c) cas64(x[kNet8[c][0]], x[kNet8[c][1]]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 42; ++c) cas64(x[kNet12[c][0]], x[kNet12[c][1]]);
+  }
 }
 
 // Accumulate dims 64H + 4J .. 64H + 4J + 3 of NR references into acc.
@@ -96,14 +110,13 @@ __device__ __forceinline__ void lane_score(float (&acc)[NR], const float4 (&v)[N
    ...);
 }
 
-// NG: 16-dim groups of the padded dimension (dp = 16 NG <= 128).
-template <int KIND, int NG>
+// NG: 16-dim groups of the padded dimension (dp = 16 NG <= 128); T: queue
+// keys per lane (8 or 12).
+template <int KIND, int NG, int T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void lane_kernel(FusedParams p) {
   constexpr int DP = 16 * NG;
   constexpr int NCH = (DP + 63) / 64;  // 64-dim chunks per row
   constexpr int NR = 4;                // references per batch
-  constexpr int T = kLaneQueue;
-  static_assert(T == 8, "the queue sort is the 8-key network");
   static_assert(NR <= T, "a batch must fit an empty queue");
   extern __shared__ __align__(16) unsigned char smem[];
 
@@ -154,15 +167,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     }
   };
 
-  float thr = __builtin_huge_valf();
+  // threshold as a bit pattern: non-negative floats (and NaN above +inf)
+  // order as unsigned integers
+  uint32_t thr = 0x7f800000u;
   int len = 0, qn = 0;
 
   // merge every lane's queue into its list (the whole wave takes part)
   auto merge = [&]() __attribute__((always_inline)) {
     uint64_t x[T];
 #pragma unroll
-    for (int s = 0; s < T; ++s) x[s] = s < qn ? X[s * kWaveSize] : kEmptyKey;
-    sort8(x);
+    for (int s = 0; s < T; ++s) {
+      const uint64_t v = X[s * kWaveSize];  // slots past the count hold stale keys
+      x[s] = s < qn ? v : kEmptyKey;
+    }
+    sort_queue<T>(x);
 #pragma unroll
     for (int s = 0; s < T; ++s) X[s * kWaveSize] = x[s];
     const int kp = min(kc, len + qn);
@@ -191,26 +209,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     }
     len = kp;
     qn = 0;
-    if (len == kc) thr = mono_value((uint32_t)(L[(kc - 1) * kWaveSize] >> 32));
+    if (len == kc) thr = (uint32_t)(L[(kc - 1) * kWaveSize] >> 32) & 0x7fffffffu;
   };
 
   // queue the batch's scores that pass the threshold; merge if the next
   // batch might not fit some lane's queue
   auto select = [&](const float (&acc)[NR], int64_t r0) __attribute__((always_inline)) {
-    float sc[NR];
-    bool any = false;
+    uint32_t sc[NR];  // score bit patterns; NaN past the end of the slice
+    uint32_t mn = 0xffffffffu;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-      sc[i] = r0 + i < s1 ? acc[i] : __builtin_nanf("");
-      any |= sc[i] <= thr;
+      sc[i] = r0 + i < s1 ? __float_as_uint(acc[i]) : 0x7fc00000u;
+      mn = min(mn, sc[i]);
     }
-    if (__builtin_amdgcn_ballot_w64(any)) {
+    if (__builtin_amdgcn_ballot_w64(mn <= thr)) {
+      // branch-free append: every key is written at the current count,
+      // which advances only for a passing score (a failing key is
+      // overwritten or lies past the count)
 #pragma unroll
-      for (int i = 0; i < NR; ++i)
-        if (sc[i] <= thr) {
-          X[qn * kWaveSize] = make_key(sc[i], (uint32_t)(r0 + i));
-          ++qn;
-        }
+      for (int i = 0; i < NR; ++i) {
+        X[qn * kWaveSize] = ((uint64_t)(sc[i] | 0x80000000u) << 32) | (uint32_t)(r0 + i);
+        qn += sc[i] <= thr ? 1 : 0;
+      }
       if (__builtin_amdgcn_ballot_w64(qn > T - NR)) merge();
     }
   };
@@ -240,15 +260,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
 }
 
 // dynamic LDS of one workgroup of `waves` waves: list and queue slots per lane
-__host__ __device__ constexpr size_t lane_lds_bytes(int waves, int kc_max) {
-  return (size_t)waves * kWaveSize * (size_t)(kc_max + kLaneQueue) * 8;
+__host__ __device__ constexpr size_t lane_lds_bytes(int waves, int kc_max, int queue) {
+  return (size_t)waves * kWaveSize * (size_t)(kc_max + queue) * 8;
 }
 
-template <int KIND, int NG>
+template <int KIND, int NG, int T>
 hipError_t launch_lane_one(const FusedParams& p, hipStream_t stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)lane_kernel<KIND, NG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)lane_kernel<KIND, NG, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kLdsBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
@@ -256,8 +276,8 @@ hipError_t launch_lane_one(const FusedParams& p, hipStream_t stream) {
   if (p.items && p.nitems <= 0) return hipSuccess;
   const int nq = p.waves * kWaveSize;
   dim3 grid = p.items ? dim3((unsigned)p.nitems) : dim3((unsigned)((p.one.n + nq - 1) / nq), (unsigned)p.one.P);
-  hipLaunchKernelGGL((lane_kernel<KIND, NG>), grid, dim3(p.waves * kWaveSize), lane_lds_bytes(p.waves, p.kc_max),
-                     stream, p);
+  hipLaunchKernelGGL((lane_kernel<KIND, NG, T>), grid, dim3(p.waves * kWaveSize),
+                     lane_lds_bytes(p.waves, p.kc_max, T), stream, p);
   return hipGetLastError();
 }
 
