@@ -250,11 +250,13 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
     p.dp = padded_dim(kind, d);
     p.es = 4;
   }
-  // Manhattan / infinity norm with dp <= 128: one query per lane, 64 per
-  // wave, up to 4 waves per workgroup as the LDS lists allow
-  // (KNN_FUSED_LANE=0 selects the general kernel instead)
+  // Per-lane selection with dp <= 128: Manhattan / infinity norm with one
+  // query per lane (64 per wave), float32 Euclidean on 32x32 MFMA tiles with
+  // one query per lane pair (32 per wave); up to 4 waves per workgroup as
+  // the LDS lists allow (KNN_FUSED_LANE=0 selects the general kernel instead)
   const char* elane = getenv("KNN_FUSED_LANE");
-  if (kind >= TILE_L1_F32 && p.dp <= kLaneMaxDp && !(elane && atoi(elane) == 0)) {
+  if ((kind >= TILE_L1_F32 || kind == TILE_L2_F32) && p.dp <= kLaneMaxDp && !(elane && atoi(elane) == 0)) {
+    const int qw = kind == TILE_L2_F32 ? 32 : kWaveSize;  // queries per wave
     // the (waves, queue) pair with the most resident waves per CU (two per
     // SIMD at most, for registers), the larger queue where it costs none
     int waves = 0, queue = 0, best = 0;
@@ -262,7 +264,7 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
     for (int t : {12, 8}) {
       if (eq && t != eq) continue;
       for (int w : {4, 2, 1}) {
-        if (w > 1 && (int64_t)(w / 2) * kWaveSize >= n) continue;  // no wave without a query
+        if (w > 1 && (int64_t)(w / 2) * qw >= n) continue;  // no wave without a query
         const size_t lds = lane_lds(w, kc, t);
         if (lds > (size_t)kLdsBytes) continue;
         const int resident = w * std::min<int>(8 / w, (int)(kLdsBytes / lds));
@@ -279,7 +281,7 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
       p.cb = queue;
       p.ng = p.dp / 16;
       p.nchunk = 1;
-      p.nq = waves * kWaveSize;
+      p.nq = waves * qw;
       // two waves per SIMD at most (register budget), fewer where LDS binds
       const int wg_per_cu = best / waves;
       const int64_t nqb = ceil_div(n, (int64_t)p.nq);
@@ -289,7 +291,7 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
       P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
       const int ep = env_int("KNN_FUSED_P");
       if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, m});
-      p.slice_len = round_up(ceil_div(m, P), 8);
+      p.slice_len = round_up(ceil_div(m, P), 32);
       p.P = (int)ceil_div(m, p.slice_len);
       *out = p;
       return KNN_OK;

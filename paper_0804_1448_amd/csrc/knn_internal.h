@@ -162,6 +162,9 @@ hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
 // kc keys and a queue of `cb` (8 or 12) keys in LDS
 constexpr int kLaneMaxDp = 128;
 hipError_t launch_lane(int kind, const FusedParams& p, hipStream_t stream);
+// float32 Euclidean with per-lane selection on 32x32 MFMA tiles (dp <= 128):
+// `waves` waves of 32 queries, lists as in the Manhattan kernel
+hipError_t launch_lane_l2(const FusedParams& p, hipStream_t stream);
 size_t lane_lds(int waves, int kc, int queue);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);

@@ -111,7 +111,7 @@ size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw) {
 
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream) {
   if (p.wide) return launch_wide(kind, p, stream);
-  if (p.lane) return launch_lane(kind, p, stream);
+  if (p.lane) return kind == TILE_L2_F32 ? launch_lane_l2(p, stream) : launch_lane(kind, p, stream);
   const bool s = p.kc_max <= 64 && p.cb / 4 <= 16;  // register merge only
   switch (kind) {
     case TILE_L2_F32:

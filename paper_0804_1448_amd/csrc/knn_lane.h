@@ -47,6 +47,10 @@ __device__ __forceinline__ float4 gload4(const float* ptr) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ float gload1(const float* ptr) {
+  return *(const __attribute__((address_space(1))) float*)ptr;
+}
+
 __device__ __forceinline__ float comp(const float4& v, int c) {
   return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
 }
@@ -78,6 +82,49 @@ __device__ __forceinline__ void sort_queue(uint64_t (&x)[T]) {
 #pragma unroll
     for (int c = 0; c < 42; ++c) cas64(x[kNet12[c][0]], x[kNet12[c][1]]);
   }
+}
+
+// Merge this lane's queue (qn unsorted keys at X[s * 64]) into its sorted
+// list (len keys at L[s * 64]), keeping the min(kc, len + qn) smallest; the
+// whole wave calls it, each lane on its own list.  The queue is sorted by a
+// network; b, the number of queue keys among the kept, is found by binary
+// search along the merge path; the two sorted runs are then merged in place
+// from the back, which stops once the queue run is used up (the rest of
+// the list is already in place).
+template <int T>
+__device__ __forceinline__ void lane_merge(uint64_t* L, uint64_t* X, int& len, int& qn, int kc) {
+  uint64_t x[T];
+#pragma unroll
+  for (int s = 0; s < T; ++s) {
+    const uint64_t v = X[s * kWaveSize];  // slots past the count hold stale keys
+    x[s] = s < qn ? v : kEmptyKey;
+  }
+  sort_queue<T>(x);
+#pragma unroll
+  for (int s = 0; s < T; ++s) X[s * kWaveSize] = x[s];
+  const int kp = min(kc, len + qn);
+  // the smallest b in [lo, hi] whose next queue key does not precede the
+  // list key it would displace
+  int lo = max(0, kp - len), hi = min(qn, kp);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (X[mid * kWaveSize] < L[(kp - mid - 1) * kWaveSize])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int b = lo, a = kp - lo, i = kp - 1;
+  while (b > 0) {  // position i takes the larger of L[a-1] and X[b-1]
+    const uint64_t xq = X[(b - 1) * kWaveSize];
+    const uint64_t xl = a > 0 ? L[(a - 1) * kWaveSize] : 0ull;
+    const bool take_list = a > 0 && xl > xq;
+    L[i * kWaveSize] = take_list ? xl : xq;
+    a -= take_list ? 1 : 0;
+    b -= take_list ? 0 : 1;
+    --i;
+  }
+  len = kp;
+  qn = 0;
 }
 
 // Accumulate dims 64H + 4J .. 64H + 4J + 3 of NR references into acc.
@@ -172,43 +219,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   uint32_t thr = 0x7f800000u;
   int len = 0, qn = 0;
 
-  // merge every lane's queue into its list (the whole wave takes part)
   auto merge = [&]() __attribute__((always_inline)) {
-    uint64_t x[T];
-#pragma unroll
-    for (int s = 0; s < T; ++s) {
-      const uint64_t v = X[s * kWaveSize];  // slots past the count hold stale keys
-      x[s] = s < qn ? v : kEmptyKey;
-    }
-    sort_queue<T>(x);
-#pragma unroll
-    for (int s = 0; s < T; ++s) X[s * kWaveSize] = x[s];
-    const int kp = min(kc, len + qn);
-    // b = number of queue keys among the kp kept: the smallest b in
-    // [lo, hi] whose next queue key does not precede the list key it would
-    // displace
-    int lo = max(0, kp - len), hi = min(qn, kp);
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (X[mid * kWaveSize] < L[(kp - mid - 1) * kWaveSize])
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    int b = lo, a = kp - lo, i = kp - 1;
-    // from the back: position i takes the larger of L[a-1] and X[b-1]; once
-    // the queue run is used up the list prefix is already in place
-    while (b > 0) {
-      const uint64_t xq = X[(b - 1) * kWaveSize];
-      const uint64_t xl = a > 0 ? L[(a - 1) * kWaveSize] : 0ull;
-      const bool take_list = a > 0 && xl > xq;
-      L[i * kWaveSize] = take_list ? xl : xq;
-      a -= take_list ? 1 : 0;
-      b -= take_list ? 0 : 1;
-      --i;
-    }
-    len = kp;
-    qn = 0;
+    lane_merge<T>(L, X, len, qn, kc);
     if (len == kc) thr = (uint32_t)(L[(kc - 1) * kWaveSize] >> 32) & 0x7fffffffu;
   };
 

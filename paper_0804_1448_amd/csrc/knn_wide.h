@@ -31,7 +31,6 @@
 
 namespace knn {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
 
 constexpr int kWideWaves = 8;

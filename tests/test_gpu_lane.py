@@ -1,10 +1,11 @@
-"""GPU parity of the one-query-per-lane Manhattan / infinity-norm kernel
-(padded dimension <= 128), through the C ABI.
+"""GPU parity of the per-lane-selection kernels (padded dimension <= 128),
+through the C ABI: Manhattan / infinity norm with one query per lane, and
+float32 Euclidean on 32x32 MFMA tiles with one query per lane pair.
 
 Every case is checked against the FP64 oracle (relative 1e-5 on distances,
 tie-aware indices).  Integer-grid data (all distances exact in float32, many
 exact ties) must reproduce the oracle bit for bit, tie order included.  The
-same searches through the general kernel (KNN_FUSED_LANE=0) must pass the
+same searches through the general kernels (KNN_FUSED_LANE=0) must pass the
 same checks, and forced slice counts (KNN_FUSED_P) exercise many short
 slices, slices shorter than the list, and a single slice.
 """
@@ -83,7 +84,7 @@ def data(kind, n, m, d, seed):
     return synthdata.gmm(n, d, 16, 0.05, seed, 1), synthdata.gmm(m, d, 16, 0.05, seed, 0)
 
 
-@pytest.mark.parametrize("metric", ["l1", "linf"])
+@pytest.mark.parametrize("metric", ["l2", "l1", "linf"])
 @pytest.mark.parametrize("n,m,d,k,kind", SHAPES)
 def test_lane_shapes(K, n, m, d, k, kind, metric):
     banner(f"lane n={n} m={m} d={d} k={k} {kind} {metric}")
@@ -105,26 +106,27 @@ def test_lane_integer_grid_is_exact(K, metric):
         assert np.array_equal(dist, D.astype(np.float32)), P
 
 
+@pytest.mark.parametrize("metric", ["l2", "l1"])
 @pytest.mark.parametrize("P", [1, 7, 64])
-def test_lane_forced_slices(K, P):
-    """A single slice, uneven slices, and slices of at most 8 references
-    (shorter than the 28-key lists, which then never fill)."""
-    banner(f"lane P={P}")
-    m = 500 if P == 64 else 5000
+def test_lane_forced_slices(K, P, metric):
+    """A single slice, uneven slices, and slices of 32 references (about
+    the 28-key lists, which may then never fill)."""
+    banner(f"lane P={P} {metric}")
+    m = 2000 if P == 64 else 5000
     Q, R = data("gmm", 150, m, 33, 800 + P)
-    check(Q, R, 20, "l1", *run(K, Q, R, 20, "l1", {"KNN_FUSED_P": P}))
+    check(Q, R, 20, metric, *run(K, Q, R, 20, metric, {"KNN_FUSED_P": P}))
 
 
 def test_lane_k_equals_m_is_a_permutation(K):
     banner("lane k = m")
     Q, R = data("uniform", 70, 120, 10, 91)
-    for metric in ("l1", "linf"):
+    for metric in ("l2", "l1", "linf"):
         dist, idx = run(K, Q, R, 120, metric)
         check(Q, R, 120, metric, dist, idx)
         assert np.all(np.sort(idx, axis=1) == np.arange(120)[None, :])
 
 
-@pytest.mark.parametrize("metric", ["l1", "linf"])
+@pytest.mark.parametrize("metric", ["l2", "l1", "linf"])
 def test_lane_and_general_kernels_agree_with_oracle(K, metric):
     banner(f"lane vs general {metric}")
     Q, R = data("gmm", 500, 20000, 96, 92)
@@ -132,3 +134,20 @@ def test_lane_and_general_kernels_agree_with_oracle(K, metric):
     b = run(K, Q, R, 20, metric, {"KNN_FUSED_LANE": 0})
     check(Q, R, 20, metric, *a)
     check(Q, R, 20, metric, *b)
+
+
+def test_lane_l2_integer_grid_is_exact(K):
+    """Integers in [0, 6) whose first 256 references average exactly 2.5 per
+    dimension (rows 128..255 mirror rows 0..127), so the Euclidean centre is
+    2.5, every translated value a half-integer, and every score, norm and
+    distance exact in float32: the result must equal the oracle bit for bit,
+    tie order included."""
+    banner("lane l2 integer grid")
+    Q = synthdata.integer_grid((333, 40), 0, 6, 42, 1)
+    R = synthdata.integer_grid((7000, 40), 0, 6, 42, 0)
+    R[128:256] = 5.0 - R[0:128]
+    D, I = oracle.knn(Q, R, 20, "l2")
+    for P in (0, 1, 37):
+        dist, idx = run(K, Q, R, 20, "l2", {"KNN_FUSED_P": P} if P else None)
+        assert np.array_equal(idx, I.astype(np.int32)), P
+        assert np.array_equal(dist, D.astype(np.float32)), P
