@@ -7,9 +7,9 @@
 // v_mfma_f32_32x32x2f32: references are the rows (A operand), queries the
 // columns (B operand, negated), and the rows' half norms are added to the
 // products.  The two k slots of the instruction take the two halves of the
-// padded dimension: lanes l and l + 32 hold dims [0, dp/2) and [dp/2, dp) of
-// query l % 32 in registers for the whole slice and load the same dims of
-// tile row l % 32 straight from global memory, one tile ahead.  In the
+// padded dimension: lanes l and l + 32 hold the even and the odd 16-byte
+// chunks of query l % 32 in registers for the whole slice and load the same
+// chunks of tile row l % 32 straight from global memory, one tile ahead.  In the
 // output, lane l holds query l % 32 against the 16 rows 8 (r / 4) + 4 (l / 32)
 // + r % 4 of the tile, so every lane sees one query and half of the slice.
 //
@@ -54,13 +54,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   uint64_t* X = L + (size_t)p.kc_max * kWaveSize;                                     // X[s * 64]: queue slot s
   const uint64_t* Lp = L - lane + (lane ^ 32);                                        // the partner's list
 
-  // B operand: the negated query dims half * HD + s
+  // B operand: the negated query dims 8 g + 4 half + c (16-byte chunks
+  // alternate between the lane halves, so that the two lanes of a row load
+  // adjacent chunks)
   float qv[HD];
   {
-    const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq + half * HD;
+    const float* qp = (const float*)in.Q + qsafe * (int64_t)in.ldq + 4 * half;
 #pragma unroll
     for (int g = 0; g < NL; ++g) {
-      const float4 v = gload4(qp + 4 * g);
+      const float4 v = gload4(qp + 8 * g);
       qv[4 * g] = -v.x;
       qv[4 * g + 1] = -v.y;
       qv[4 * g + 2] = -v.z;
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   // t0 + 8 g + 4 half + i (clamped to the set)
   const float* Rf = (const float*)in.R;
   auto row_part = [&](int64_t t0, int g) __attribute__((always_inline)) {
-    return gload4(Rf + min(t0 + col, s1 - 1) * (int64_t)in.ldr + half * HD + 4 * g);
+    return gload4(Rf + min(t0 + col, s1 - 1) * (int64_t)in.ldr + 8 * g + 4 * half);
   };
   auto norms = [&](int64_t t0, float4 (&nh)[4]) __attribute__((always_inline)) {
 #pragma unroll
