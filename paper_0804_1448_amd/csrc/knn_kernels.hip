@@ -275,7 +275,37 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
   for (int pl = 0; pl < in.P; ++pl) nvalid += lens[pl];
   const int nc = min(in.kprime, nvalid);
 
-  if (in.P <= 4 || in.P > 64) {
+  if (in.P <= 8 && in.kc <= 32 && in.kprime <= 32) {
+    // up to 8 lists of at most 32 keys: a bitonic merge tree in registers.
+    // Register j holds list 2j ascending in lanes 0..31 and list 2j+1
+    // descending in lanes 32..63; the lane-wise minimum across the halves is
+    // a bitonic sequence holding the 32 smallest keys of the pair, which five
+    // exchange stages sort (ascending for even j, descending for odd j, so
+    // that the next level pairs an ascending with a descending run).
+    const int i = lane & 31, up = lane >> 5;
+    uint64_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int pl = 2 * j + up, e = up ? 31 - i : i;
+      v[j] = pl < in.P && e < lens[pl] ? keys[pl * in.kc + e] : kEmptyKey;
+    }
+    auto clean32 = [&](uint64_t x, bool asc) __attribute__((always_inline)) {
+      x = bitonic_step<16>(x, lane, asc);
+      x = bitonic_step<8>(x, lane, asc);
+      x = bitonic_step<4>(x, lane, asc);
+      x = bitonic_step<2>(x, lane, asc);
+      return bitonic_step<1>(x, lane, asc);
+    };
+    const int nreg = (in.P + 1) / 2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nreg) v[j] = clean32(min(v[j], xor_lane64<32>(v[j], lane)), (j & 1) == 0);
+    // level 2: runs 0 (ascending) and 1 (descending), 2 and 3, lane-wise
+    if (nreg > 1) v[0] = clean32(min(v[0], v[1]), true);
+    if (nreg > 2) v[2] = clean32(min(v[2], nreg > 3 ? v[3] : kEmptyKey), false);
+    if (nreg > 2) v[0] = clean32(min(v[0], v[2]), true);
+    if (lane < nc) cand[lane] = (uint32_t)v[0];
+  } else if (in.P <= 4 || in.P > 64) {
     // few lists: each key's merged position by binary searches in the others
     for (int e = lane; e < T; e += 64) {
       const int pl = e / in.kc, i = e - pl * in.kc;
