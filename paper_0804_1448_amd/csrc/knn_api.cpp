@@ -371,7 +371,11 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
 
   const size_t cbytes = centre_refs ? (size_t)round_up((int64_t)a.d * 4, 256) : 0;
   const size_t pbytes0 = 0;
-  const size_t rbytes = prep_refs ? (size_t)round_up(a.m * plan.dp * plan.es, 256) : 0;
+  // the float32 Euclidean lane kernel reads one-shot references in the
+  // 32-row tile layout (whole tiles allocated)
+  const bool tiled = one_shot && plan.lane && a.kind == TILE_L2_F32;
+  const int64_t mrows = tiled ? round_up(a.m, (int64_t)32) : a.m;
+  const size_t rbytes = prep_refs ? (size_t)round_up(mrows * plan.dp * plan.es, 256) : 0;
   const size_t hbytes = prep_refs && l2 ? (size_t)round_up(a.m * 4, 256) : 0;
   const size_t qbytes = prep_q ? (size_t)round_up(a.n * plan.dp * plan.es, 256) : 0;
   const size_t kbytes = (size_t)round_up(a.n * plan.P * (int64_t)plan.kc * 8, 256);
@@ -397,9 +401,13 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   if (one_shot) {
     if (prep_refs) {
       TimedLaunch tl("prep_refs", a.stream);
-      HIP_TRY(launch_prep_rows(a.R32, a.m, a.d, a.d, centre, wrows, plan.dp, elem_of_kind(a.kind),
-                               l2 ? wrhalf : nullptr, a.stream),
-              "reference preparation launch");
+      if (tiled)
+        HIP_TRY(launch_prep_rows_tiled(a.R32, a.m, a.d, a.d, centre, (float*)wrows, plan.dp, wrhalf, a.stream),
+                "reference preparation launch");
+      else
+        HIP_TRY(launch_prep_rows(a.R32, a.m, a.d, a.d, centre, wrows, plan.dp, elem_of_kind(a.kind),
+                                 l2 ? wrhalf : nullptr, a.stream),
+                "reference preparation launch");
       rows = wrows;
       rhalf = l2 ? wrhalf : nullptr;
     } else {
@@ -442,6 +450,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   fp.kc_max = plan.kc;
   fp.wide = plan.wide ? 1 : 0;
   fp.lane = plan.lane ? 1 : 0;
+  fp.tiled = tiled ? 1 : 0;
   {
     TimedLaunch tl(fused_name(a.kind), a.stream);
     HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");

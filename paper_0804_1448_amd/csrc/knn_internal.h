@@ -78,7 +78,8 @@ struct FusedParams {
   int waves;            // waves per workgroup
   int kc_max;           // largest kc of the launch (sizes the LDS lists)
   int wide;             // 1: the 32x32-tile Euclidean kernel with register lists (ng = dp / 16)
-  int lane;             // 1: the one-query-per-lane vector-ALU kernel (ng = dp / 16, 64 queries per wave)
+  int lane;             // 1: a per-lane-selection kernel (ng = dp / 16; cb = queue keys per lane)
+  int tiled;            // float32 Euclidean lane kernel: R in the 32-row tile layout (launch_prep_rows_tiled)
 };
 
 // One instance of the merge + exact re-rank + finalize kernel.
@@ -140,6 +141,10 @@ constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
 // status of the launch.
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst,
                             int ldd, int elem, float* rhalf, hipStream_t stream);
+// float32 rows in the 32-row tile layout [i / 32][t / 4][i % 32][t % 4]
+// (ldd a multiple of 4; dst holds round_up(rows, 32) rows)
+hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds, const float* centre, float* dst,
+                                  int ldd, float* rhalf, hipStream_t stream);
 hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* centre, hipStream_t stream);
 size_t fused_lds_bytes(int kind, int waves, int kc, int cb, int cw);
 hipError_t launch_fused(int kind, const FusedParams& p, hipStream_t stream);

@@ -53,7 +53,10 @@ hipError_t launch_centre(const float* src, int64_t rows, int d, int lds, float* 
 // One wave per row: copy (float32) or round (bf16/f16, nearest even) a row,
 // minus `centre` if given, into a zero-padded row of `ldd` elements and, if
 // `rhalf` is set, store half the squared norm of the stored (rounded) row.
-template <int E>
+// TILED (float32 only): element t of row i goes to the 32-row tile layout
+// [i / 32][t / 4][i % 32][t % 4], in which the same 16 bytes of 32
+// consecutive rows are contiguous.
+template <int E, bool TILED = false>
 __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict__ src, int64_t rows, int d,
                                                         int lds, const float* __restrict__ centre,
                                                         void* __restrict__ dst, int ldd,
@@ -67,7 +70,8 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
     float v = t < d ? (centre ? s[t] - centre[t] : s[t]) : 0.f;
     float stored;
     if constexpr (E == ELEM_F32) {
-      ((float*)dst)[row * ldd + t] = v;
+      const int64_t at = TILED ? (((row >> 5) * (ldd >> 2) + (t >> 2)) << 7) + ((row & 31) << 2) + (t & 3) : row * ldd + t;
+      ((float*)dst)[at] = v;
       stored = v;
     } else if constexpr (E == ELEM_BF16) {
       uint16_t b = f32_to_bf16_rne(v);
@@ -85,6 +89,14 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) rhalf[row] = 0.5f * acc;
   }
+}
+
+hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds, const float* centre, float* dst,
+                                  int ldd, float* rhalf, hipStream_t stream) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL((prep_rows_kernel<ELEM_F32, true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, src,
+                     rows, d, lds, centre, (void*)dst, ldd, rhalf);
+  return hipGetLastError();
 }
 
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst, int ldd,

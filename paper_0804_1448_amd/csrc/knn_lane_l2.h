@@ -26,7 +26,10 @@
 namespace knn {
 
 // NG: 16-dim groups of the padded dimension (dp = 16 NG); T: queue keys.
-template <int NG, int T>
+// TILED: R in the 32-row tile layout, where each 16-byte load instruction of
+// a wave reads 1 KB of contiguous memory (row-major rows: 32 rows, 32 bytes
+// each).
+template <int NG, int T, bool TILED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void lane_l2_kernel(FusedParams p) {
   constexpr int HD = 8 * NG;  // dims per lane half
   constexpr int NL = HD / 4;  // 16-byte loads per half row
@@ -75,7 +78,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   // t0 + 8 g + 4 half + i (clamped to the set)
   const float* Rf = (const float*)in.R;
   auto row_part = [&](int64_t t0, int g) __attribute__((always_inline)) {
-    return gload4(Rf + min(t0 + col, s1 - 1) * (int64_t)in.ldr + 8 * g + 4 * half);
+    if constexpr (TILED) {  // tiles past the slice end read the last tile of the slice
+      const int64_t tile = min(t0, s1 - 1) >> 5;
+      return gload4(Rf + ((tile * (2 * NL) + 2 * g + half) * 32 + col) * 4);
+    } else {
+      return gload4(Rf + min(t0 + col, s1 - 1) * (int64_t)in.ldr + 8 * g + 4 * half);
+    }
   };
   auto norms = [&](int64_t t0, float4 (&nh)[4]) __attribute__((always_inline)) {
 #pragma unroll
@@ -173,19 +181,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   }
 }
 
-template <int NG, int T>
+template <int NG, int T, bool TILED>
 hipError_t launch_lane_l2_one(const FusedParams& p, hipStream_t stream) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)lane_l2_kernel<NG, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kLdsBytes);
+    hipError_t e = hipFuncSetAttribute((const void*)lane_l2_kernel<NG, T, TILED>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   if (p.items && p.nitems <= 0) return hipSuccess;
   const int nq = p.waves * 32;
   dim3 grid = p.items ? dim3((unsigned)p.nitems) : dim3((unsigned)((p.one.n + nq - 1) / nq), (unsigned)p.one.P);
-  hipLaunchKernelGGL((lane_l2_kernel<NG, T>), grid, dim3(p.waves * kWaveSize), lane_lds_bytes(p.waves, p.kc_max, T),
+  hipLaunchKernelGGL((lane_l2_kernel<NG, T, TILED>), grid, dim3(p.waves * kWaveSize), lane_lds_bytes(p.waves, p.kc_max, T),
                      stream, p);
   return hipGetLastError();
 }
