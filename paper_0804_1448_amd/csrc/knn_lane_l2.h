@@ -85,30 +85,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
       return gload4(Rf + min(t0 + col, s1 - 1) * (int64_t)in.ldr + 8 * g + 4 * half);
     }
   };
+  // Rows past the end of the slice get a NaN norm, which makes their scores
+  // NaN: no comparison accepts them.
   auto norms = [&](int64_t t0, float4 (&nh)[4]) __attribute__((always_inline)) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int64_t r0 = t0 + 8 * g + 4 * half;
-      if (r0 + 3 < in.m) {
+      if (r0 + 3 < s1) {
         nh[g] = gload4(in.rhalf + r0);
       } else {
         const int64_t last = in.m - 1;
-        nh[g] = make_float4(gload1(in.rhalf + min(r0, last)), gload1(in.rhalf + min(r0 + 1, last)),
-                            gload1(in.rhalf + min(r0 + 2, last)), gload1(in.rhalf + min(r0 + 3, last)));
+        const float nan = __builtin_nanf("");
+        nh[g] = make_float4(r0 < s1 ? gload1(in.rhalf + min(r0, last)) : nan,
+                            r0 + 1 < s1 ? gload1(in.rhalf + min(r0 + 1, last)) : nan,
+                            r0 + 2 < s1 ? gload1(in.rhalf + min(r0 + 2, last)) : nan,
+                            r0 + 3 < s1 ? gload1(in.rhalf + min(r0 + 3, last)) : nan);
       }
     }
   };
 
-  float thr = __builtin_huge_valf();
+  // threshold as a monotone score code (the high word of a key): +inf
+  // until the list is full; NaN, the score of rows past the end of the slice,
+  // codes above +inf and never passes
+  uint32_t thr = 0xff800000u;
   int len = 0, qn = 0;
 
   auto merge = [&]() __attribute__((always_inline)) {
     lane_merge<T>(L, X, len, qn, kc);
     __builtin_amdgcn_wave_barrier();
     const int plen = (int)xor_lane32<32>((uint32_t)len, lane);
-    float t = thr;
-    if (len == kc) t = fminf(t, mono_value((uint32_t)(L[(kc - 1) * kWaveSize] >> 32)));
-    if (plen == kc) t = fminf(t, mono_value((uint32_t)(Lp[(kc - 1) * kWaveSize] >> 32)));
+    uint32_t t = thr;
+    if (len == kc) t = min(t, (uint32_t)(L[(kc - 1) * kWaveSize] >> 32));
+    if (plen == kc) t = min(t, (uint32_t)(Lp[(kc - 1) * kWaveSize] >> 32));
     thr = t;
   };
 
@@ -117,17 +125,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   auto select = [&](const f32x16& acc, int64_t t0) __attribute__((always_inline)) {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const int64_t rb = t0 + 8 * g + 4 * half;
-      float sc[4];
+      const uint32_t rb = (uint32_t)(t0 + 8 * g + 4 * half);
+      uint32_t code[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sc[i] = rb + i < s1 ? acc[4 * g + i] : __builtin_nanf("");
-      const float mn = fminf(fminf(sc[0], sc[1]), fminf(sc[2], sc[3]));
+      for (int i = 0; i < 4; ++i) code[i] = mono_code(acc[4 * g + i]);
+      const uint32_t mn = min(min(code[0], code[1]), min(code[2], code[3]));
       if (__builtin_amdgcn_ballot_w64(mn <= thr)) {
         // branch-free append (a failing key is overwritten or lies past the count)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          X[qn * kWaveSize] = make_key(sc[i], (uint32_t)(rb + i));
-          qn += sc[i] <= thr ? 1 : 0;
+          X[qn * kWaveSize] = ((uint64_t)code[i] << 32) | (rb + (uint32_t)i);
+          qn += code[i] <= thr ? 1 : 0;
         }
         if (__builtin_amdgcn_ballot_w64(qn > T - 4)) merge();
       }
