@@ -12,6 +12,24 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
 
+// Loads through the global address space: the compiler counts them on
+// vmcnt alone (a flat load also counts on lgkmcnt, which forces a full wait
+// before every LDS access and defeats loads issued ahead of their use).
+__device__ __forceinline__ float4 gload4(const float* ptr) {
+  const f32x4 v = *(const __attribute__((address_space(1))) f32x4*)ptr;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ float gload1(const float* ptr) {
+  return *(const __attribute__((address_space(1))) float*)ptr;
+}
+
+__device__ __forceinline__ uint4 gload16(const void* ptr) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = *(const __attribute__((address_space(1))) u32x4*)ptr;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // float -> monotone unsigned code: a < b as floats (non-NaN) iff code(a) < code(b)
 __device__ __forceinline__ uint32_t mono_code(float f) {
   uint32_t u = __float_as_uint(f);

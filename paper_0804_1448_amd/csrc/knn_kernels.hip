@@ -38,8 +38,10 @@ __global__ __launch_bounds__(256) void centre_kernel(const float* __restrict__ s
   const int j = blockIdx.x * 64 + dl;
   const int used = (int)(rows < kCentreRows ? rows : kCentreRows);
   float acc = 0.f;
-  if (j < d)
+  if (j < d) {
+#pragma unroll 16
     for (int i = ph; i < used; i += 4) acc += src[(int64_t)i * lds + j];
+  }
   red[ph][dl] = acc;
   __syncthreads();
   if (ph == 0 && j < d) centre[j] = (((red[0][dl] + red[1][dl]) + red[2][dl]) + red[3][dl]) / (float)used;
@@ -199,17 +201,17 @@ __device__ __forceinline__ float exact_distance_run(const float* q, bool qvec, c
     }
   };
   auto qload4 = [&](int t) __attribute__((always_inline)) {
-    if (qvec && t + 4 <= d) return *(const float4*)(q + t);
-    return make_float4(t < d ? q[t] : 0.f, t + 1 < d ? q[t + 1] : 0.f, t + 2 < d ? q[t + 2] : 0.f,
-                       t + 3 < d ? q[t + 3] : 0.f);
+    if (qvec && t + 4 <= d) return gload4(q + t);
+    return make_float4(t < d ? gload1(q + t) : 0.f, t + 1 < d ? gload1(q + t + 1) : 0.f,
+                       t + 2 < d ? gload1(q + t + 2) : 0.f, t + 3 < d ? gload1(q + t + 3) : 0.f);
   };
   for (int t = first; t < d; t += stride) {
     if (type == ELEM_F32) {
-      const float4 rv = *(const float4*)((const float*)rm + roff + t);
+      const float4 rv = gload4((const float*)rm + roff + t);
       const float4 qv = qload4(t);
       acc4(qv.x - rv.x, qv.y - rv.y, qv.z - rv.z, qv.w - rv.w);
     } else {
-      const uint4 rv = *(const uint4*)((const uint16_t*)rm + roff + t);
+      const uint4 rv = gload16((const uint16_t*)rm + roff + t);
       const uint32_t w[4] = {rv.x, rv.y, rv.z, rv.w};
       float r8[8];
 #pragma unroll
@@ -370,6 +372,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
     const int sub = lane & 15, grp = lane >> 4;
     const int run = in.rm_type == ELEM_F32 ? 4 : 8;  // dims per lane and pass
     const bool qvec = ((uintptr_t)qrow % 16) == 0;
+#pragma unroll 2
     for (int j0 = 0; j0 < nc; j0 += 4) {
       const int j = j0 + grp;
       const uint32_t r = j < nc ? cand[j] : 0u;

@@ -39,18 +39,6 @@ __device__ __forceinline__ float row_bcast(float v) {  // lane J of this lane's 
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + J, 0xF, 0xF, true));
 }
 
-// 16-byte load through the global address space: the compiler then counts
-// it on vmcnt alone (a flat load also counts on lgkmcnt, which forces a full
-// wait before every LDS access and defeats the one-batch-ahead loads)
-__device__ __forceinline__ float4 gload4(const float* ptr) {
-  const f32x4 v = *(const __attribute__((address_space(1))) f32x4*)ptr;
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-
-__device__ __forceinline__ float gload1(const float* ptr) {
-  return *(const __attribute__((address_space(1))) float*)ptr;
-}
-
 __device__ __forceinline__ float comp(const float4& v, int c) {
   return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
 }
