@@ -581,6 +581,42 @@ def bench_serve(args):
 
 
 # ------------------------------------------------------------------- copy
+# ---------------------------------------------------------------- entropy
+def bench_entropy(args):
+    """k-NN entropy estimate (knn_entropy) of the default workload's reference
+    set: a self search for the k + 1 nearest of all 16384 points plus the
+    per-point logarithms and the fixed-order sum.  Pairs/s counts the n*n
+    pairs the self search scores."""
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    R, _, p = synthdata.workload("gmm16384_d96")
+    n, d, k = R.shape[0], R.shape[1], p["k"]
+    Yd = torch.from_numpy(R).cuda()
+    hs = []
+    sec, kernels = timed(K, torch, lambda: hs.append(K.entropy(Yd, k)), args.steps, args.warmup)
+    log(f"[bench] entropy of {n} x {d} (k = {k}): {sec * 1e3:.4f} ms, estimate {hs[-1]:.6f} nats")
+    result = {"metric": "query-ref pairs/sec", "value": float(n) * n / sec, "unit": "pairs/s", "n_gpus": 1,
+              "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": "entropy_gmm16384_d96", "n": n, "d": d, "k": k},
+              "estimate_nats": hs[-1], "kernels": kernels}
+    if not args.no_cpu_baseline:
+        from oracle import entropy as E
+
+        t0 = time.perf_counter()
+        h_ref = E.entropy_knn(R, k, threads=host_threads())
+        cpu_s = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": float(n) * n / cpu_s, "unit": "pairs/s", "cores": host_threads(),
+                                  "kind": "oracle", "sample": f"the whole estimate (FP64), {cpu_s:.2f} s"}
+        result["parity_vs_oracle"] = {"oracle_nats": h_ref, "abs_err": abs(hs[-1] - h_ref), "tol": d * 1e-5,
+                                      "ok": abs(hs[-1] - h_ref) <= d * 1e-5}
+        log(f"[bench] oracle {h_ref:.6f} nats, |difference| {abs(hs[-1] - h_ref):.2e}")
+    return result
+
+
 def bench_copy(args):
     import torch
 
@@ -603,7 +639,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy"])
+    ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy", "entropy"])
     ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
@@ -622,7 +658,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
               "across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3)}
+    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -636,7 +672,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     fn = {"pairs": bench_pairs, "precision": bench_precision, "batched": bench_batched, "serve": bench_serve,
-          "copy": bench_copy}
+          "copy": bench_copy, "entropy": bench_entropy}
     print(json.dumps(fn[args.mode](args)), flush=True)
 
 

@@ -89,6 +89,30 @@ int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, 
                int32_t metric, float* dist, int32_t* idx, void* stream);
 
 /*
+ * knn_entropy -- k-nearest-neighbour entropy estimate of a point set, the
+ * entropy-estimation application of Section 2.2 (Eq. (3)-(5)).  With
+ * rho_k(y_i) the Euclidean distance from y_i to its k-th nearest neighbour
+ * among the other n - 1 points,
+ *   H = (1/n) sum_i [ d log rho_k(y_i) + log(n - 1) ] + log c_1(d) - Psi(k),
+ * c_1(d) = 2 pi^(d/2) / (d Gamma(d/2)) the unit-ball volume, Psi the digamma
+ * function.  Eq. (3) is read with rho_k^d (the estimator of Goria et al. that
+ * the paper cites; the printed log((n-1) rho_k) lacks the power d).
+ *   Y [n][d]: device float32 points, at once the queries and the references.
+ *   k: 1 <= k <= n - 1.
+ *   out: device pointer to one double; receives the estimate in nats (-inf
+ *     when some point has k others at distance 0).
+ * The k + 1 nearest of every point (itself included) come from the float32
+ * search of knn_search; the point's own entry is dropped.  The per-point
+ * logarithms are summed in double precision in a fixed order, so the result
+ * is deterministic.  Scratch of n (k + 1) 8 + n 8 bytes is allocated and
+ * released in stream order on `stream`.
+ * Errors: KNN_ERR_INVALID for n < 2, k out of range, d < 1 or a NULL pointer;
+ * KNN_ERR_OOM if the scratch cannot be allocated; KNN_ERR_DEVICE if a launch
+ * fails.
+ */
+int knn_entropy(const float* Y, int64_t n, int32_t d, int32_t k, double* out, void* stream);
+
+/*
  * knn_create_refs -- prepare a resident reference set (the reference side of
  * the distance computation of Section 2.1, done once).
  *   R [m][d]: device float32 input; it is copied, so the caller may free it

@@ -18,7 +18,7 @@ import torch
 from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
                    ServerStats, check, load)
 
-__all__ = ["search", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
+__all__ = ["search", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
            "timing"]
 
 KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
@@ -89,6 +89,18 @@ def search(Q: torch.Tensor, R: torch.Tensor, k: int, metric: str = "l2", out=Non
                          METRICS[metric], ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
                          _stream_ptr(stream)))
     return dist, idx
+
+
+def entropy(Y: torch.Tensor, k: int, stream=None) -> float:
+    """k-NN entropy estimate of the points Y [n, d] in nats (knn_entropy):
+    (1/n) sum_i [d log rho_k(y_i) + log(n - 1)] + log c_1(d) - Psi(k)."""
+    lib = load()
+    Y = _points(Y, "Y")
+    n, d = Y.shape
+    out = torch.empty(1, dtype=torch.float64, device=Y.device)
+    check(lib.knn_entropy(ctypes.c_void_p(Y.data_ptr()), n, d, int(k), ctypes.c_void_p(out.data_ptr()),
+                          _stream_ptr(stream)))
+    return float(out.item())
 
 
 class Refs:

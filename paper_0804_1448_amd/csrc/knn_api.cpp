@@ -1,6 +1,7 @@
 // knn_api.cpp -- C ABI of the k-NN library: argument checks, launch plans,
 // workspaces and reference-set handles.  Every computation runs in the HIP
 // kernels of knn_kernels.hip.
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -612,6 +613,38 @@ int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, 
   a.idx = idx;
   a.stream = (hipStream_t)stream;
   return run_search(a);
+}
+
+int knn_entropy(const float* Y, int64_t n, int32_t d, int32_t k, double* out, void* stream) {
+  if (n < 2) return fail(KNN_ERR_INVALID, "n = %lld: the estimate needs at least two points", (long long)n);
+  if (k < 1 || (int64_t)k > n - 1) return fail(KNN_ERR_INVALID, "k = %d outside [1, n - 1 = %lld]", k, (long long)(n - 1));
+  if (d < 1) return fail(KNN_ERR_INVALID, "d = %d: dimension must be >= 1", d);
+  int st;
+  if ((st = check_ptr(Y, "Y")) || (st = check_ptr(out, "out"))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t kk = (int64_t)k + 1;
+  const size_t dbytes = round_up(n * kk * 4, 256), ibytes = round_up(n * kk * 4, 256), tbytes = n * 8;
+  void* scratch = nullptr;
+  if (hipMallocAsync(&scratch, dbytes + ibytes + tbytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(KNN_ERR_OOM, "cannot allocate %zu bytes of entropy scratch", dbytes + ibytes + tbytes);
+  }
+  float* dist = (float*)scratch;
+  int32_t* idx = (int32_t*)((unsigned char*)scratch + dbytes);
+  double* terms = (double*)((unsigned char*)scratch + dbytes + ibytes);
+  st = knn_search(Y, n, Y, n, d, k + 1, KNN_L2, dist, idx, stream);
+  if (st == KNN_OK) {
+    // log c_1(d) = log 2 + (d/2) log pi - log d - log Gamma(d/2); Psi(k) = -gamma + sum_{j<k} 1/j
+    double psi = -0.57721566490153286060651209008240243;
+    for (int j = 1; j < k; ++j) psi += 1.0 / j;
+    const double logc1 = std::log(2.0) + 0.5 * d * std::log(M_PI) - std::log((double)d) - std::lgamma(0.5 * d);
+    const double offset = std::log((double)(n - 1)) + logc1 - psi;
+    const hipError_t e = launch_entropy(dist, idx, n, k, terms, (double)d / (double)n, offset, out, s);
+    if (e != hipSuccess) st = hip_fail(e, "entropy launch");
+  }
+  const hipError_t ef = hipFreeAsync(scratch, s);
+  if (st == KNN_OK && ef != hipSuccess) st = hip_fail(ef, "entropy scratch release");
+  return st;
 }
 
 int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage, int32_t keep_fp32_master, void* stream,

@@ -172,6 +172,11 @@ hipError_t launch_lane(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_lane_l2(const FusedParams& p, hipStream_t stream);
 size_t lane_lds(int waves, int kc, int queue);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
+// k-NN entropy: per-point log rho_k from the k + 1 nearest (dist/idx
+// [n][k + 1]) into terms[n], then out = scale * sum(terms) + offset
+hipError_t launch_entropy(const float* dist, const int32_t* idx, int64_t n, int k, double* terms, double scale,
+                          double offset, double* out, hipStream_t stream);
+
 hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
 size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);
 

@@ -428,6 +428,48 @@ size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max) {
   return finalize_wave_bytes(keys_max, p_max, kprime_max) * kFinalWaves;
 }
 
+// ------------------------------------------------ k-NN entropy estimate
+// log rho_k(y_i) for every point from its k + 1 nearest in (distance, index)
+// order: the point's own entry (distance 0) is dropped, which leaves the k-th
+// other neighbour at position k if the point was among the k + 1, else at
+// position k - 1 (then k + 1 other points lie at distance 0).
+__global__ __launch_bounds__(256) void entropy_terms_kernel(const float* __restrict__ dist,
+                                                            const int32_t* __restrict__ idx, int64_t n, int k,
+                                                            double* __restrict__ terms) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t row = i * (int64_t)(k + 1);
+  bool self = false;
+  for (int j = 0; j <= k; ++j) self |= idx[row + j] == (int32_t)i;
+  terms[i] = log((double)dist[row + (self ? k : k - 1)]);
+}
+
+// out = scale * (sum of terms) + offset: one workgroup, each thread a fixed
+// strided subset in order, then a fixed tree over the threads
+__global__ __launch_bounds__(1024) void entropy_sum_kernel(const double* __restrict__ terms, int64_t n, double scale,
+                                                           double offset, double* __restrict__ out) {
+  __shared__ double part[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += terms[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = scale * part[0] + offset;
+}
+
+hipError_t launch_entropy(const float* dist, const int32_t* idx, int64_t n, int k, double* terms, double scale,
+                          double offset, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(entropy_terms_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, dist, idx, n, k,
+                     terms);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(entropy_sum_kernel, dim3(1), dim3(1024), 0, stream, terms, n, scale, offset, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ batched point preparation
 // One wave per row over the concatenated rows of several arrays; a row's
 // job is found by binary search over the jobs' first rows.
