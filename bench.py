@@ -617,6 +617,48 @@ def bench_entropy(args):
     return result
 
 
+# ------------------------------------------------------------ Mahalanobis
+def bench_mahalanobis(args):
+    """knn_search_mahalanobis on the default workload's points with a seeded
+    general covariance (Sigma = A A^T / d + I, L its inverse's Cholesky
+    factor): the mapping of Q and R by L^T plus the Euclidean search."""
+    import numpy as np
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    R, Q, p = synthdata.workload("gmm16384_d96")
+    n, m, d, k = Q.shape[0], R.shape[0], R.shape[1], p["k"]
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((d, d))
+    L = np.linalg.cholesky(np.linalg.inv(A @ A.T / d + np.eye(d))).astype(np.float32)
+    Qd, Rd, Ld = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (Q, R, L))
+    out = [None]
+    sec, kernels = timed(K, torch, lambda: out.__setitem__(0, K.search_mahalanobis(Qd, Rd, Ld, k)), args.steps,
+                         args.warmup)
+    log(f"[bench] Mahalanobis {n} x {m} x {d} (k = {k}): {sec * 1e3:.4f} ms, {n * m / sec:.4e} pairs/s")
+    result = {"metric": "query-ref pairs/sec", "value": float(n) * m / sec, "unit": "pairs/s", "n_gpus": 1,
+              "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": "mahalanobis_gmm16384_d96", "n": n, "m": m, "d": d, "k": k}, "kernels": kernels}
+    if not args.no_cpu_baseline:
+        from oracle.mahalanobis import knn_mahalanobis
+
+        rows = np.sort(np.random.default_rng(5).choice(n, 64, replace=False))
+        t0 = time.perf_counter()
+        D, _ = knn_mahalanobis(Q[rows], R, L.astype(np.float64), k)
+        cpu_s = time.perf_counter() - t0
+        dist, idx = (t.cpu().numpy() for t in out[0])
+        err = float(np.max(np.abs(dist[rows] - D) / np.maximum(D, 1e-30)))
+        result["cpu_baseline"] = {"value": float(len(rows)) * m / cpu_s, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"{len(rows)} seeded queries against all {m} references (numpy FP64), "
+                                            f"{cpu_s:.2f} s"}
+        result["parity_vs_oracle"] = {"queries": len(rows), "max_rel_err_dist": err, "ok": err <= 1e-5}
+        log(f"[bench] oracle sample: {len(rows)} queries, max relative distance error {err:.2e}")
+    return result
+
+
 def bench_copy(args):
     import torch
 
@@ -639,7 +681,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy", "entropy"])
+    ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy", "entropy",
+                                                      "mahalanobis"])
     ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
@@ -658,7 +701,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
               "across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3)}
+    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -672,7 +715,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     fn = {"pairs": bench_pairs, "precision": bench_precision, "batched": bench_batched, "serve": bench_serve,
-          "copy": bench_copy, "entropy": bench_entropy}
+          "copy": bench_copy, "entropy": bench_entropy, "mahalanobis": bench_mahalanobis}
     print(json.dumps(fn[args.mode](args)), flush=True)
 
 

@@ -89,6 +89,27 @@ int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, 
                int32_t metric, float* dist, int32_t* idx, void* stream);
 
 /*
+ * knn_search_mahalanobis -- brute force under a Mahalanobis distance, one of
+ * the distances the problem definition of Section 2.1 names:
+ *   d_M(q, r) = sqrt((q - r)^T Sigma^-1 (q - r)) = ||L^T (q - r)||,
+ * with L a factor of the inverse covariance, Sigma^-1 = L L^T.
+ *   Q [n][d], R [m][d]: device float32 inputs; L [d][d]: device float32,
+ *     row-major (L[t][j] at t * d + j), supplied by the caller (for example
+ *     the Cholesky factor of Sigma^-1).
+ *   dist [n][k], idx [n][k]: device outputs, as for knn_search.
+ * Q and R are translated by the mean of R's first 256 rows and mapped by
+ * L^T in float32 (one fused multiply-add per term, ascending t); the
+ * Euclidean search of knn_search then runs on the mapped points.  Distances
+ * are exact float32 difference-form distances of the mapped points, so they
+ * differ from the FP64 d_M by the rounding of the mapping (a relative error
+ * of about d 2^-24 |L^T (x - c)| / d_M).
+ * Scratch of (n + m) d 4 bytes is allocated and released in stream order.
+ * Errors: as knn_search; KNN_ERR_INVALID also for a NULL L.
+ */
+int knn_search_mahalanobis(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, const float* L, int32_t k,
+                           float* dist, int32_t* idx, void* stream);
+
+/*
  * knn_entropy -- k-nearest-neighbour entropy estimate of a point set, the
  * entropy-estimation application of Section 2.2 (Eq. (3)-(5)).  With
  * rho_k(y_i) the Euclidean distance from y_i to its k-th nearest neighbour

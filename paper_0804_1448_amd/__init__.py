@@ -18,7 +18,7 @@ import torch
 from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
                    ServerStats, check, load)
 
-__all__ = ["search", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
+__all__ = ["search", "search_mahalanobis", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
            "timing"]
 
 KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
@@ -88,6 +88,24 @@ def search(Q: torch.Tensor, R: torch.Tensor, k: int, metric: str = "l2", out=Non
     check(lib.knn_search(ctypes.c_void_p(Q.data_ptr()), n, ctypes.c_void_p(R.data_ptr()), m, d, int(k),
                          METRICS[metric], ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
                          _stream_ptr(stream)))
+    return dist, idx
+
+
+def search_mahalanobis(Q: torch.Tensor, R: torch.Tensor, L: torch.Tensor, k: int, out=None, stream=None):
+    """Brute force under d_M(q, r) = ||L^T (q - r)|| (knn_search_mahalanobis),
+    L [d, d] float32 on the device with Sigma^-1 = L L^T."""
+    lib = load()
+    Q = _points(Q, "Q")
+    R = _points(R, "R")
+    L = _points(L, "L")
+    n, d = Q.shape
+    m = R.shape[0]
+    if R.shape[1] != d or tuple(L.shape) != (d, d):
+        raise ValueError("Q [n,d], R [m,d] and L [d,d] required")
+    dist, idx = _outputs(n, k, Q.device, out)
+    check(lib.knn_search_mahalanobis(ctypes.c_void_p(Q.data_ptr()), n, ctypes.c_void_p(R.data_ptr()), m, d,
+                                     ctypes.c_void_p(L.data_ptr()), int(k), ctypes.c_void_p(dist.data_ptr()),
+                                     ctypes.c_void_p(idx.data_ptr()), _stream_ptr(stream)))
     return dist, idx
 
 

@@ -615,6 +615,34 @@ int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, 
   return run_search(a);
 }
 
+int knn_search_mahalanobis(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, const float* L, int32_t k,
+                           float* dist, int32_t* idx, void* stream) {
+  int st = check_common(n, m, d, k, KNN_L2);
+  if (st != KNN_OK) return st;
+  if (n == 0) return KNN_OK;
+  if ((st = check_ptr(Q, "Q")) || (st = check_ptr(R, "R")) || (st = check_ptr(L, "L")) ||
+      (st = check_ptr(dist, "dist")) || (st = check_ptr(idx, "idx")))
+    return st;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t cbytes = round_up((int64_t)d * 4, 256), qbytes = round_up(n * d * 4, 256),
+               rbytes = round_up(m * d * 4, 256);
+  void* scratch = nullptr;
+  if (hipMallocAsync(&scratch, cbytes + qbytes + rbytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(KNN_ERR_OOM, "cannot allocate %zu bytes of Mahalanobis scratch", cbytes + qbytes + rbytes);
+  }
+  float* c = (float*)scratch;
+  float* Qt = (float*)((unsigned char*)scratch + cbytes);
+  float* Rt = (float*)((unsigned char*)scratch + cbytes + qbytes);
+  hipError_t e = launch_centre(R, m, d, d, c, s);
+  if (e == hipSuccess) e = launch_transform_rows(Q, n, d, c, L, Qt, s);
+  if (e == hipSuccess) e = launch_transform_rows(R, m, d, c, L, Rt, s);
+  st = e == hipSuccess ? knn_search(Qt, n, Rt, m, d, k, KNN_L2, dist, idx, stream) : hip_fail(e, "Mahalanobis transform");
+  const hipError_t ef = hipFreeAsync(scratch, s);
+  if (st == KNN_OK && ef != hipSuccess) st = hip_fail(ef, "Mahalanobis scratch release");
+  return st;
+}
+
 int knn_entropy(const float* Y, int64_t n, int32_t d, int32_t k, double* out, void* stream) {
   if (n < 2) return fail(KNN_ERR_INVALID, "n = %lld: the estimate needs at least two points", (long long)n);
   if (k < 1 || (int64_t)k > n - 1) return fail(KNN_ERR_INVALID, "k = %d outside [1, n - 1 = %lld]", k, (long long)(n - 1));

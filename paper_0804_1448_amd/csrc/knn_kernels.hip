@@ -428,6 +428,31 @@ size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max) {
   return finalize_wave_bytes(keys_max, p_max, kprime_max) * kFinalWaves;
 }
 
+// ------------------------------------------------ Mahalanobis transform
+// Y[i][j] = sum_t (X[i][t] - c[t]) L[t][j]: rows mapped by L^T after a common
+// translation by c (which cancels in every difference), one thread per output
+// element, the sum in ascending t with fused multiply-adds.
+__global__ __launch_bounds__(256) void transform_rows_kernel(const float* __restrict__ X, int64_t rows, int d,
+                                                             const float* __restrict__ c,
+                                                             const float* __restrict__ L, float* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * d) return;
+  const int64_t i = e / d;
+  const int j = (int)(e - i * d);
+  const float* x = X + i * d;
+  float acc = 0.f;
+  for (int t = 0; t < d; ++t) acc = fmaf(x[t] - c[t], L[(int64_t)t * d + j], acc);
+  Y[e] = acc;
+}
+
+hipError_t launch_transform_rows(const float* X, int64_t rows, int d, const float* c, const float* L, float* Y,
+                                 hipStream_t stream) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transform_rows_kernel, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, stream, X, rows,
+                     d, c, L, Y);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ k-NN entropy estimate
 // log rho_k(y_i) for every point from its k + 1 nearest in (distance, index)
 // order: the point's own entry (distance 0) is dropped, which leaves the k-th
