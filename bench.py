@@ -659,6 +659,46 @@ def bench_mahalanobis(args):
     return result
 
 
+# ---------------------------------------------------------- classification
+def bench_classify(args):
+    """knn_classify on the default workload: the 64 mixture components are
+    the classes of the 16384 references; each of the 16384 queries takes the
+    majority class of its k = 20 nearest."""
+    import numpy as np
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    p = dict(synthdata.WORKLOADS["gmm16384_d96"])
+    R, lab = synthdata.gmm(p["m"], p["d"], p["comps"], p["sigma"], p["wid"], synthdata.ROLE_REFS, return_labels=True)
+    Q = synthdata.gmm(p["n"], p["d"], p["comps"], p["sigma"], p["wid"], synthdata.ROLE_QUERIES)
+    n, m, d, k = p["n"], p["m"], p["d"], p["k"]
+    Qd, Rd = torch.from_numpy(Q).cuda(), torch.from_numpy(R).cuda()
+    labd = torch.from_numpy(lab.astype(np.int32)).cuda()
+    out = [None]
+    sec, kernels = timed(K, torch, lambda: out.__setitem__(0, K.classify(Qd, Rd, labd, k)), args.steps, args.warmup)
+    log(f"[bench] classify {n} x {m} x {d} (k = {k}, {p['comps']} classes): {sec * 1e3:.4f} ms, "
+        f"{n * m / sec:.4e} pairs/s")
+    result = {"metric": "query-ref pairs/sec", "value": float(n) * m / sec, "unit": "pairs/s", "n_gpus": 1,
+              "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+              "config": {"workload": "classify_gmm16384_d96", "n": n, "m": m, "d": d, "k": k, "classes": p["comps"]},
+              "kernels": kernels}
+    if not args.no_cpu_baseline:
+        from oracle import classify as C
+
+        t0 = time.perf_counter()
+        ref = C.classify(Q, R, lab, k, threads=host_threads())
+        cpu_s = time.perf_counter() - t0
+        agree = float(np.mean(out[0].cpu().numpy() == ref))
+        result["cpu_baseline"] = {"value": float(n) * m / cpu_s, "unit": "pairs/s", "cores": host_threads(),
+                                  "kind": "oracle", "sample": f"all {n} queries (FP64), {cpu_s:.2f} s"}
+        result["parity_vs_oracle"] = {"agreement": agree}
+        log(f"[bench] agreement with the oracle's votes: {agree:.6f}")
+    return result
+
+
 def bench_copy(args):
     import torch
 
@@ -682,7 +722,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy", "entropy",
-                                                      "mahalanobis"])
+                                                      "mahalanobis", "classify"])
     ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
@@ -701,7 +741,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
               "across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3)}
+    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -715,7 +755,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     fn = {"pairs": bench_pairs, "precision": bench_precision, "batched": bench_batched, "serve": bench_serve,
-          "copy": bench_copy, "entropy": bench_entropy, "mahalanobis": bench_mahalanobis}
+          "copy": bench_copy, "entropy": bench_entropy, "mahalanobis": bench_mahalanobis,
+          "classify": bench_classify}
     print(json.dumps(fn[args.mode](args)), flush=True)
 
 

@@ -110,6 +110,21 @@ int knn_search_mahalanobis(const float* Q, int64_t n, const float* R, int64_t m,
                            float* dist, int32_t* idx, void* stream);
 
 /*
+ * knn_classify -- k-NN classification, the classification application of
+ * Section 2.2: each query takes the class most represented among its k
+ * nearest references (Euclidean, the float32 search of knn_search).  Where
+ * classes tie, the class of the nearest neighbour among the tied classes wins
+ * (neighbours in (distance, index) order).
+ *   Q [n][d], R [m][d]: device float32 inputs.
+ *   labels [m]: device int32 class of every reference (any values).
+ *   out [n]: device int32 predicted classes.
+ * Scratch of 2 n k 4 bytes is allocated and released in stream order.
+ * Errors: as knn_search; KNN_ERR_INVALID also for NULL labels or out.
+ */
+int knn_classify(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, const int32_t* labels, int32_t k,
+                 int32_t* out, void* stream);
+
+/*
  * knn_entropy -- k-nearest-neighbour entropy estimate of a point set, the
  * entropy-estimation application of Section 2.2 (Eq. (3)-(5)).  With
  * rho_k(y_i) the Euclidean distance from y_i to its k-th nearest neighbour

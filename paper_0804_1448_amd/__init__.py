@@ -18,7 +18,7 @@ import torch
 from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
                    ServerStats, check, load)
 
-__all__ = ["search", "search_mahalanobis", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
+__all__ = ["search", "search_mahalanobis", "classify", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
            "timing"]
 
 KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
@@ -107,6 +107,25 @@ def search_mahalanobis(Q: torch.Tensor, R: torch.Tensor, L: torch.Tensor, k: int
                                      ctypes.c_void_p(L.data_ptr()), int(k), ctypes.c_void_p(dist.data_ptr()),
                                      ctypes.c_void_p(idx.data_ptr()), _stream_ptr(stream)))
     return dist, idx
+
+
+def classify(Q: torch.Tensor, R: torch.Tensor, labels: torch.Tensor, k: int, stream=None) -> torch.Tensor:
+    """Majority class of each query's k nearest references (knn_classify);
+    labels: int32 [m] on the device.  Returns int32 [n]."""
+    lib = load()
+    Q = _points(Q, "Q")
+    R = _points(R, "R")
+    if Q.shape[1] != R.shape[1]:
+        raise ValueError("Q and R differ in dimension")
+    if labels.dtype != torch.int32 or labels.dim() != 1 or labels.shape[0] != R.shape[0] or labels.device.type != "cuda":
+        raise ValueError("labels must be an int32 [m] tensor on the GPU")
+    labels = labels.contiguous()
+    n, d = Q.shape
+    out = torch.empty(n, dtype=torch.int32, device=Q.device)
+    check(lib.knn_classify(ctypes.c_void_p(Q.data_ptr()), n, ctypes.c_void_p(R.data_ptr()), R.shape[0], d,
+                           ctypes.c_void_p(labels.data_ptr()), int(k), ctypes.c_void_p(out.data_ptr()),
+                           _stream_ptr(stream)))
+    return out
 
 
 def entropy(Y: torch.Tensor, k: int, stream=None) -> float:

@@ -21,6 +21,8 @@ SIGNATURES = {
                               _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "knn_search_mahalanobis": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
                                           _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "knn_classify": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
+                                _c.c_int32, _c.c_void_p, _c.c_void_p]),
     "knn_entropy": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p]),
     "knn_create_refs": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
                                    _c.POINTER(_c.c_void_p)]),

@@ -643,6 +643,33 @@ int knn_search_mahalanobis(const float* Q, int64_t n, const float* R, int64_t m,
   return st;
 }
 
+int knn_classify(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, const int32_t* labels, int32_t k,
+                 int32_t* out, void* stream) {
+  int st = check_common(n, m, d, k, KNN_L2);
+  if (st != KNN_OK) return st;
+  if (n == 0) return KNN_OK;
+  if ((st = check_ptr(Q, "Q")) || (st = check_ptr(R, "R")) || (st = check_ptr(labels, "labels")) ||
+      (st = check_ptr(out, "out")))
+    return st;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t dbytes = round_up(n * (int64_t)k * 4, 256);
+  void* scratch = nullptr;
+  if (hipMallocAsync(&scratch, 2 * dbytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(KNN_ERR_OOM, "cannot allocate %zu bytes of classification scratch", 2 * dbytes);
+  }
+  float* dist = (float*)scratch;
+  int32_t* idx = (int32_t*)((unsigned char*)scratch + dbytes);
+  st = knn_search(Q, n, R, m, d, k, KNN_L2, dist, idx, stream);
+  if (st == KNN_OK) {
+    const hipError_t e = launch_vote(idx, n, k, labels, out, s);
+    if (e != hipSuccess) st = hip_fail(e, "vote launch");
+  }
+  const hipError_t ef = hipFreeAsync(scratch, s);
+  if (st == KNN_OK && ef != hipSuccess) st = hip_fail(ef, "classification scratch release");
+  return st;
+}
+
 int knn_entropy(const float* Y, int64_t n, int32_t d, int32_t k, double* out, void* stream) {
   if (n < 2) return fail(KNN_ERR_INVALID, "n = %lld: the estimate needs at least two points", (long long)n);
   if (k < 1 || (int64_t)k > n - 1) return fail(KNN_ERR_INVALID, "k = %d outside [1, n - 1 = %lld]", k, (long long)(n - 1));

@@ -172,6 +172,9 @@ hipError_t launch_lane(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_lane_l2(const FusedParams& p, hipStream_t stream);
 size_t lane_lds(int waves, int kc, int queue);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
+// k-NN classification: out[q] = majority of labels[idx[q][0..k-1]] (ties to
+// the nearest of the tied classes)
+hipError_t launch_vote(const int32_t* idx, int64_t n, int k, const int32_t* labels, int32_t* out, hipStream_t stream);
 // Mahalanobis: Y = (X - c) L for rows of X [rows][d], c [d], L [d][d] (row-major)
 hipError_t launch_transform_rows(const float* X, int64_t rows, int d, const float* c, const float* L, float* Y,
                                  hipStream_t stream);

@@ -453,6 +453,37 @@ hipError_t launch_transform_rows(const float* X, int64_t rows, int d, const floa
   return hipGetLastError();
 }
 
+// ------------------------------------------------ k-NN classification
+// Majority label of each query's k nearest (idx [n][k], nearest first): the
+// count of neighbour j's label among the k, maximised over j; the first j
+// (nearest) with the top count wins, so a tie between classes goes to the
+// class of the nearest neighbour among the tied classes.  One thread per
+// query, k^2 label comparisons.
+__global__ __launch_bounds__(256) void vote_kernel(const int32_t* __restrict__ idx, int64_t n, int k,
+                                                   const int32_t* __restrict__ labels, int32_t* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int32_t* row = idx + q * (int64_t)k;
+  int best = -1, best_count = 0;
+  for (int j = 0; j < k; ++j) {
+    const int32_t lj = labels[row[j]];
+    int c = 0;
+    for (int t = 0; t < k; ++t) c += labels[row[t]] == lj ? 1 : 0;
+    if (c > best_count) {
+      best_count = c;
+      best = lj;
+    }
+  }
+  out[q] = best;
+}
+
+hipError_t launch_vote(const int32_t* idx, int64_t n, int k, const int32_t* labels, int32_t* out,
+                       hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vote_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, idx, n, k, labels, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ k-NN entropy estimate
 // log rho_k(y_i) for every point from its k + 1 nearest in (distance, index)
 // order: the point's own entry (distance 0) is dropped, which leaves the k-th

@@ -1,0 +1,79 @@
+"""GPU parity of k-NN classification (knn_classify) against the oracle's
+majority vote, through the C ABI.
+
+The predicted class depends on the neighbour set, which the search returns
+tie-aware (an index may differ from the oracle's only where another reference
+lies within the tolerance at that rank).  So the check is split: the vote
+kernel must give exactly the oracle's vote (oracle/classify.py) over the
+neighbours the GPU search returns, and those neighbours must pass the
+search's tie-aware check against the FP64 oracle.  The hand-worked votes on
+the line must come out exactly.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synthdata
+from oracle import classify as C
+from oracle.check import compare
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+
+    import paper_0804_1448_amd as K
+
+    assert torch.cuda.is_available()
+    K.load()
+    return K
+
+
+def banner(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype=None):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).cuda()
+
+
+def test_hand_worked_votes(K):
+    import torch
+
+    with open(os.path.join(HERE, "golden", "classify_line.json")) as f:
+        g = json.load(f)
+    R = np.array(g["references"], dtype=np.float32)[:, None]
+    lab = dev(np.array(g["labels"], dtype=np.int32))
+    for c in g["cases"]:
+        Q = np.array([[c["query"]]], dtype=np.float32)
+        assert int(K.classify(dev(Q), dev(R), lab, c["k"]).cpu()[0]) == c["label"], c
+    del torch
+
+
+@pytest.mark.parametrize("n,m,d,k,comps", [(500, 8000, 16, 5, 10), (300, 5000, 64, 20, 32), (257, 3001, 3, 1, 4),
+                                           (100, 20000, 128, 50, 64), (64, 700, 8, 100, 3)])
+def test_votes_match_oracle(K, n, m, d, k, comps):
+    banner(f"classify n={n} m={m} d={d} k={k} classes={comps}")
+    R, lab = synthdata.gmm(m, d, comps, 0.15, 990 + d, 0, return_labels=True)
+    Q = synthdata.gmm(n, d, comps, 0.15, 990 + d, 1)
+    pred = K.classify(dev(Q), dev(R), dev(lab.astype(np.int32)), k).cpu().numpy()
+    dist, idx = (t.cpu().numpy() for t in K.search(dev(Q), dev(R), k, "l2"))
+    rep = compare(Q, R, k, "l2", dist, idx, tol=1e-5)
+    assert rep["ok"], rep
+    expect = np.array([C.vote(lab[row]) for row in idx])
+    assert np.array_equal(pred, expect)
+    # and against the oracle's own neighbour sets wherever those agree
+    oracle_pred = C.classify(Q, R, lab, k)
+    assert np.mean(pred == oracle_pred) >= 0.99
