@@ -699,6 +699,58 @@ def bench_classify(args):
     return result
 
 
+# ------------------------------------------------------------- timing table
+def bench_table(args):
+    """The timing table of the paper's experiments, reshaped for this GPU:
+    N query and N reference points (uniform [0,1) floats, seeded), D dims,
+    k = 20, Euclidean, for N in 1200 .. 38400 and D in 8 .. 96.  Each cell is
+    timed end to end (inputs in pinned host memory copied in, results copied
+    back) and device-resident, over a few repetitions."""
+    import torch
+
+    import paper_0804_1448_amd as K
+    import synthdata
+
+    Ns = [1200, 2400, 4800, 9600, 19200, 38400]
+    Ds = [8, 16, 32, 64, 80, 96]
+    k, reps = 20, max(3, args.steps)
+    cells = []
+    for D in Ds:
+        for N in Ns:
+            R = synthdata.uniform((N, D), 1000 + D, 0)
+            Q = synthdata.uniform((N, D), 1000 + D, 1)
+            Rh, Qh = torch.from_numpy(R).pin_memory(), torch.from_numpy(Q).pin_memory()
+            dh = torch.empty((N, k), dtype=torch.float32).pin_memory()
+            ih = torch.empty((N, k), dtype=torch.int32).pin_memory()
+            Rd, Qd = Rh.cuda(), Qh.cuda()
+
+            def e2e():
+                Rx = Rh.to("cuda", non_blocking=True)
+                Qx = Qh.to("cuda", non_blocking=True)
+                dist, idx = K.search(Qx, Rx, k, "l2")
+                dh.copy_(dist, non_blocking=True)
+                ih.copy_(idx, non_blocking=True)
+
+            times = {}
+            for name, fn in (("end_to_end", e2e), ("resident", lambda: K.search(Qd, Rd, k, "l2"))):
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                torch.cuda.synchronize()
+                times[name] = (time.perf_counter() - t0) / reps
+            cells.append({"N": N, "D": D, "end_to_end_ms": times["end_to_end"] * 1e3,
+                          "resident_ms": times["resident"] * 1e3})
+            log(f"[bench] D={D:3d} N={N:6d}: end to end {times['end_to_end'] * 1e3:8.3f} ms, "
+                f"resident {times['resident'] * 1e3:8.3f} ms")
+    big = [c for c in cells if c["N"] == Ns[-1] and c["D"] == Ds[-1]][0]
+    return {"metric": "query-ref pairs/sec", "value": float(Ns[-1]) ** 2 / (big["resident_ms"] / 1e3),
+            "unit": "pairs/s", "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": big["resident_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "table_uniform", "N": Ns, "D": Ds, "k": k, "distance": "l2"}, "cells": cells}
+
+
 def bench_copy(args):
     import torch
 
@@ -722,7 +774,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy", "entropy",
-                                                      "mahalanobis", "classify"])
+                                                      "mahalanobis", "classify", "table"])
     ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
@@ -741,7 +793,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
               "across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3)}
+    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3), "table": (5, 1)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -756,7 +808,7 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     fn = {"pairs": bench_pairs, "precision": bench_precision, "batched": bench_batched, "serve": bench_serve,
           "copy": bench_copy, "entropy": bench_entropy, "mahalanobis": bench_mahalanobis,
-          "classify": bench_classify}
+          "classify": bench_classify, "table": bench_table}
     print(json.dumps(fn[args.mode](args)), flush=True)
 
 
