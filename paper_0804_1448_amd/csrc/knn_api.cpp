@@ -208,7 +208,9 @@ int env_int(const char* name) {
   return v ? atoi(v) : 0;
 }
 
-int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
+// tiled_refs: the references can be prepared in the 32-row tile layout (one-shot
+// searches), which makes the float32 lane kernel the faster one up to far longer slices
+int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Plan* out) {
   Plan p;
   p.kind = kind;
   p.kc = kc;
@@ -238,9 +240,12 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, Plan* out) {
     p.slice_len = round_up(ceil_div(m, P), kStepRefs);
     p.P = (int)ceil_div(m, p.slice_len);
     // Float32 steps are long, so the 32x32 kernel pays off only where its
-    // per-query merges (twice the queries per wave of the general kernel)
-    // are spread over a long scan; short slices keep the general kernel.
-    if (!(kind == TILE_L2_F32 && p.slice_len < kWideMinSliceF32)) {
+    // per-query merges are spread over a long scan; shorter slices take the
+    // float32 lane kernel (or the general kernel), and one-shot searches,
+    // whose references the lane kernel reads in the tile layout, keep the
+    // 32x32 kernel only for the longest scans.
+    const int64_t min_f32 = tiled_refs && p.dp <= kLaneMaxDp ? kWideMinSliceF32Tiled : kWideMinSliceF32;
+    if (!(kind == TILE_L2_F32 && p.slice_len < min_f32)) {
       *out = p;
       return KNN_OK;
     }
@@ -358,7 +363,7 @@ int elem_of_kind(int kind) {
 // ws == nullptr only the needed size is stored in *need.
 int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need) {
   Plan plan;
-  int st = make_plan(a.kind, a.n, a.m, a.d, a.kprime, &plan);
+  int st = make_plan(a.kind, a.n, a.m, a.d, a.kprime, a.R32 != nullptr, &plan);
   if (st != KNN_OK) return st;
   const bool l2 = a.kind <= TILE_L2_F16;
   const bool one_shot = a.R32 != nullptr;

@@ -160,6 +160,10 @@ constexpr int kWideQueries = 256;
 constexpr int kWideMaxKc = 64;
 constexpr int kWideMaxDp = 128;
 constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice worth the 32x32 kernel
+// the same when the references can be read in the 32-row tile layout by the
+// float32 lane kernel (measured: the lane kernel wins at slices of 16384 and
+// 19200, the 32x32 kernel at 2^20)
+constexpr int64_t kWideMinSliceF32Tiled = 131072;
 constexpr size_t kWideLdsBytes = 149 * 1024;  // static LDS of the widest instantiation, rounded up
 hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
 // Manhattan / infinity-norm kernel with one query per lane (dp <= 128):

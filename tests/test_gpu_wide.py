@@ -137,24 +137,35 @@ def test_wide_and_general_kernels_agree_with_oracle(K):
 @pytest.mark.parametrize("n,m,d,k", [(4096, 262144, 64, 20), (100, 1048576, 32, 20), (64, 600000, 100, 56),
                                      (700, 9000, 96, 20)])
 def test_wide_fp32_matches_oracle_and_general(K, n, m, d, k):
-    """Float32 Euclidean (k + 8 <= 64, d <= 128): slices of at least 16384
-    references run the 32x32-tile kernel, shorter ones the general kernel;
-    the same search with the general kernel forced (KNN_FUSED_WIDE=0) must
-    pass the same oracle check (on a query sample for the larger cases)."""
+    """Float32 Euclidean (k + 8 <= 64, d <= 128) on a resident float32 set:
+    slices of at least 16384 references run the 32x32-tile kernel, shorter
+    ones the lane kernel; the same search with the 32x32 kernel switched off
+    (KNN_FUSED_WIDE=0), and the one-shot search (which keeps the 32x32 kernel
+    for slices of 131072+ only), must pass the same oracle check (on a query
+    sample for the larger cases)."""
     import torch
 
     banner(f"wide fp32 n={n} m={m} d={d} k={k}")
     Q = synthdata.gmm(n, d, 64, 0.08, 500 + d + k, 1)
     R = synthdata.gmm(m, d, 64, 0.08, 500 + d + k, 0, threads=8)
     Qd, Rd = torch.from_numpy(Q).cuda(), torch.from_numpy(R).cuda()
-    a = [t.cpu().numpy() for t in K.search(Qd, Rd, k, "l2")]
+    refs = K.Refs(Rd, storage="fp32")
+
+    def resident():
+        out = [t.cpu().numpy() for t in refs.search(Qd, k, "l2")]
+        torch.cuda.synchronize()
+        return out
+
+    a = resident()
     os.environ["KNN_FUSED_WIDE"] = "0"
     try:
-        b = [t.cpu().numpy() for t in K.search(Qd, Rd, k, "l2")]
+        b = resident()
     finally:
         del os.environ["KNN_FUSED_WIDE"]
+    c = [t.cpu().numpy() for t in K.search(Qd, Rd, k, "l2")]
+    refs.close()
     rows = np.arange(n) if n * m <= 2e8 else np.random.default_rng(5).choice(n, 48, replace=False)
     ref = oracle.knn(Q[rows], R, k, "l2")
-    for dist, idx in (a, b):
+    for dist, idx in (a, b, c):
         rep = compare(Q, R, k, "l2", dist, idx, tol=TOL, ref=ref, rows=rows)
         assert rep["ok"], rep
