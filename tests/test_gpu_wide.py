@@ -137,12 +137,13 @@ def test_wide_and_general_kernels_agree_with_oracle(K):
 @pytest.mark.parametrize("n,m,d,k", [(4096, 262144, 64, 20), (100, 1048576, 32, 20), (64, 600000, 100, 56),
                                      (700, 9000, 96, 20)])
 def test_wide_fp32_matches_oracle_and_general(K, n, m, d, k):
-    """Float32 Euclidean (k + 8 <= 64, d <= 128) on a resident float32 set:
-    slices of at least 16384 references run the 32x32-tile kernel, shorter
-    ones the lane kernel; the same search with the 32x32 kernel switched off
-    (KNN_FUSED_WIDE=0), and the one-shot search (which keeps the 32x32 kernel
-    for slices of 131072+ only), must pass the same oracle check (on a query
-    sample for the larger cases)."""
+    """Float32 Euclidean (k + 8 <= 64, d <= 128).  Resident set with the lane
+    kernels switched off (KNN_FUSED_LANE=0): slices of at least 16384
+    references run the 32x32-tile kernel, shorter ones the general kernel.
+    Resident set by default: the 32x32-tile kernel from 16384, the lane kernel
+    (row-major rows) below.  One-shot search: the lane kernel on tiled rows up
+    to slices of 131072, then the 32x32-tile kernel.  All three must pass the
+    same oracle check (on a query sample for the larger cases)."""
     import torch
 
     banner(f"wide fp32 n={n} m={m} d={d} k={k}")
@@ -156,12 +157,12 @@ def test_wide_fp32_matches_oracle_and_general(K, n, m, d, k):
         torch.cuda.synchronize()
         return out
 
-    a = resident()
-    os.environ["KNN_FUSED_WIDE"] = "0"
+    os.environ["KNN_FUSED_LANE"] = "0"
     try:
-        b = resident()
+        a = resident()
     finally:
-        del os.environ["KNN_FUSED_WIDE"]
+        del os.environ["KNN_FUSED_LANE"]
+    b = resident()
     c = [t.cpu().numpy() for t in K.search(Qd, Rd, k, "l2")]
     refs.close()
     rows = np.arange(n) if n * m <= 2e8 else np.random.default_rng(5).choice(n, 48, replace=False)
