@@ -270,6 +270,7 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Pl
     for (int t : {12, 8}) {
       if (eq && t != eq) continue;
       for (int w : {4, 2, 1}) {
+        if (ew && w != ew) continue;
         if (w > 1 && (int64_t)(w / 2) * qw >= n) continue;  // no wave without a query
         const size_t lds = lane_lds(w, kc, t);
         if (lds > (size_t)kLdsBytes) continue;
