@@ -7,7 +7,9 @@ computes one by one:
   with 32 extra candidates and the exact float32 re-rank, and the resident
   float32 search of the same sets (which must pass the strict check);
 * the batched form: 512 instances of uneven m, n, d and k, FP16 tiles +
-  re-rank, autotuned, replayed from a HIP graph.
+  re-rank, autotuned, replayed from a HIP graph;
+* the serving form: four resident FP16 sets of 1-4 Mi points, requests of
+  the serving trace batched together, each equal to the request alone.
 
 Bars: no invalid or repeated index; recall@k >= 0.999 for the 16-bit tiles;
 distances of the hits within relative 1e-5 of the oracle's; the float32
@@ -148,4 +150,55 @@ def test_batched_form_full_size(K):
     finally:
         b.close()
         for r in keep:
+            r.close()
+
+
+def test_serving_form_full_size(K):
+    """Four resident FP16 sets of 1-4 Mi points (d = 128); 48 requests of the
+    serving trace submitted at once, so that they are batched together and
+    their batches overlap on the device.  Each result must equal the same
+    request searched alone, bit for bit, and match the oracle on the sets'
+    float16-rounded rows (the canonical rows of FP16 storage) on its first
+    rows."""
+    import torch
+
+    import oracle
+
+    spec = dict(synthdata.SERVE4)
+    th = threads()
+    extra = 14
+    banner(f"serving form: sets {spec['sets']} d={spec['d']}, fp16 + {extra} extra candidates")
+    sets, pools = [], []
+    for j in range(len(spec["sets"])):
+        Rd = torch.from_numpy(synthdata.serve_set(j, spec, threads=th)).cuda()
+        sets.append(K.Refs(Rd, storage="fp16", keep_fp32_master=False))
+        del Rd
+        pools.append(synthdata.serve_queries(j, spec))
+    trace = synthdata.serve_requests(48, spec)
+    try:
+        with K.Server(sets, mem_budget=8 << 30, max_batches=4, max_queue=4096, max_batch_queries=8192,
+                      precision="fp16", s_extra=extra) as srv:
+            tickets = [srv.submit(s, pools[s][off:off + n], k) for _, s, off, n, k in trace]
+            got = [srv.wait(t) for t in tickets]
+            st = srv.stats()
+        assert st["completed"] == len(trace)
+        canon = {}
+        recall_num = recall_den = 0.0
+        for j, ((_, s, off, n, k), (gd, gi, _)) in enumerate(zip(trace, got)):
+            Q = pools[s][off:off + n]
+            wd, wi = sets[s].search(torch.from_numpy(Q).cuda(), k, "l2", precision="fp16", s_extra=extra)
+            torch.cuda.synchronize()
+            assert np.array_equal(wd.cpu().numpy(), gd) and np.array_equal(wi.cpu().numpy(), gi), f"request {j}"
+            if j % 4 == 0:
+                if s not in canon:
+                    canon[s] = synthdata.serve_set(s, spec, threads=th).astype(np.float16).astype(np.float32)
+                rows = np.arange(min(n, 8))
+                rep = compare(Q, canon[s], k, "l2", gd, gi, tol=TOL,
+                              ref=oracle.knn(Q[rows], canon[s], k, "l2", threads=th), rows=rows)
+                assert rep["bad_index_rows"] == 0 and rep["max_rel_err_hits"] <= TOL, (j, rep)
+                recall_num += rep["recall"] * len(rows)
+                recall_den += len(rows)
+        assert recall_num / recall_den >= 0.999, recall_num / recall_den
+    finally:
+        for r in sets:
             r.close()
