@@ -15,10 +15,13 @@
 //
 // Selection is per lane, as in the Manhattan kernel (knn_lane.h): a sorted
 // list and a queue per lane in LDS, merged by lane_merge.  A lane filters
-// with the smaller of its own list's kc-th score and its partner lane's
-// (l ^ 32, the same query's other half): both bound the query's kc-th best
-// from above.  At the end of the slice lane l < 32 merges the two lists of
-// its query into the slice's output list.
+// with an upper bound of its query's kc-th best key so far, from its own list
+// and its partner lane's (l ^ 32, the same query's other half): either list's
+// kc-th key, and, once the lists hold i and kc - i keys, the larger of their
+// i-th and (kc - i)-th keys (kc keys lie at or below it), which tracks the
+// query's kc-th best over the whole slice rather than over half of it.  At the
+// end of the slice lane l < 32 merges the two lists of its query into the
+// slice's output list.
 #pragma once
 
 #include "knn_lane.h"
@@ -104,11 +107,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     }
   };
 
-  // threshold as a monotone score code (the high word of a key): +inf
-  // until the list is full; NaN, the score of rows past the end of the slice,
-  // codes above +inf and never passes
+  // threshold as a monotone score code (the high word of a key), +inf until
+  // the lists fill, and as the float it codes.  Scores are filtered with
+  // float compares, which NaN (the score of rows past the end of the slice)
+  // never passes; -0 and +0 compare equal there, so a key coded just above the
+  // threshold may enter the queue, and the merge, which keeps the kc smallest
+  // keys, drops it.
   uint32_t thr = 0xff800000u;
+  float thr_f = __builtin_inff();
   int len = 0, qn = 0;
+  const int ki = kc / 2, kj = kc - kc / 2;  // the split of the two-list bound
 
   auto merge = [&]() __attribute__((always_inline)) {
     lane_merge<T>(L, X, len, qn, kc);
@@ -117,7 +125,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     uint32_t t = thr;
     if (len == kc) t = min(t, (uint32_t)(L[(kc - 1) * kWaveSize] >> 32));
     if (plen == kc) t = min(t, (uint32_t)(Lp[(kc - 1) * kWaveSize] >> 32));
+    if (ki > 0 && len >= ki && plen >= kj)
+      t = min(t, max((uint32_t)(L[(ki - 1) * kWaveSize] >> 32), (uint32_t)(Lp[(kj - 1) * kWaveSize] >> 32)));
     thr = t;
+    thr_f = mono_value(t);
   };
 
   // queue the tile's scores that pass the threshold, four rows at a time;
@@ -126,16 +137,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const uint32_t rb = (uint32_t)(t0 + 8 * g + 4 * half);
-      uint32_t code[4];
+      bool pass[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) code[i] = mono_code(acc[4 * g + i]);
-      const uint32_t mn = min(min(code[0], code[1]), min(code[2], code[3]));
-      if (__builtin_amdgcn_ballot_w64(mn <= thr)) {
+      for (int i = 0; i < 4; ++i) pass[i] = acc[4 * g + i] <= thr_f;
+      if (__builtin_amdgcn_ballot_w64(pass[0] || pass[1] || pass[2] || pass[3])) {
         // branch-free append (a failing key is overwritten or lies past the count)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          X[qn * kWaveSize] = ((uint64_t)code[i] << 32) | (rb + (uint32_t)i);
-          qn += code[i] <= thr ? 1 : 0;
+          X[qn * kWaveSize] = ((uint64_t)mono_code(acc[4 * g + i]) << 32) | (rb + (uint32_t)i);
+          qn += pass[i] ? 1 : 0;
         }
         if (__builtin_amdgcn_ballot_w64(qn > T - 4)) merge();
       }
