@@ -91,6 +91,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   // Rows past the end of the slice get a NaN norm, which makes their scores
   // NaN: no comparison accepts them.
   auto norms = [&](int64_t t0, float4 (&nh)[4]) __attribute__((always_inline)) {
+    if (t0 + QW <= s1) {  // the whole tile lies in the slice (wave-uniform)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) nh[g] = gload4(in.rhalf + t0 + 8 * g + 4 * half);
+      return;
+    }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const int64_t r0 = t0 + 8 * g + 4 * half;
