@@ -39,6 +39,16 @@ constexpr int kWideQueriesWG = kWideWaves * kWideQueriesPerWave;  // queries per
 static_assert(kWideQueriesWG == kWideQueries, "host and kernel agree on the query block");
 constexpr int kWideMaxKeys = 64;                              // list capacity: one key per lane
 
+// Minimum of three scores with v_min3_f32 as it stands.  The scores come from
+// matrix instructions or are the quiet NaN that marks rows past the end of
+// the slice, which the instruction passes over like fminf; fminf itself would
+// first canonicalize every operand.
+__device__ __forceinline__ float min3_raw(float a, float b, float c) {
+  float r;
+  asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG; even
 // for the 16-bit kinds, whose rows are padded to 32).
 template <int KIND, int NKG>
@@ -254,11 +264,12 @@ __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      float mq[4];
+        float mq[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        mq[q] = fminf(fminf(acc[t][4 * q], acc[t][4 * q + 1]), fminf(acc[t][4 * q + 2], acc[t][4 * q + 3]));
-      const float mn = fminf(fminf(mq[0], mq[1]), fminf(mq[2], mq[3]));
+        mq[q] = min3_raw(min3_raw(acc[t][4 * q], acc[t][4 * q + 1], acc[t][4 * q + 2]), acc[t][4 * q + 3],
+                         acc[t][4 * q + 3]);
+      const float mn = min3_raw(min3_raw(mq[0], mq[1], mq[2]), mq[3], mq[3]);
       if (ballot(mn <= thr)) {
         const int bound = 4 * ((mq[0] <= thr) + (mq[1] <= thr) + (mq[2] <= thr) + (mq[3] <= thr));
         const uint64_t ov = ballot(lcnt + bound > SUB);
