@@ -372,7 +372,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalParams p) {
     const int sub = lane & 15, grp = lane >> 4;
     const int run = in.rm_type == ELEM_F32 ? 4 : 8;  // dims per lane and pass
     const bool qvec = ((uintptr_t)qrow % 16) == 0;
-#pragma unroll 2
     for (int j0 = 0; j0 < nc; j0 += 4) {
       const int j = j0 + grp;
       const uint32_t r = j < nc ? cand[j] : 0u;
