@@ -118,8 +118,9 @@ def timed(K, torch, fn, steps, warmup):
     return (t1 - t0) / steps, kernel_table(K)
 
 
-def oracle_sample(Q, R, k, metrics, target_s, seed=12345, max_rows=None):
-    """Time the oracle on a query sample sized to about ``target_s`` host seconds."""
+def oracle_sample(Q, R, k, metrics, target_s, seed=12345, max_rows=None, min_rows=None):
+    """Time the oracle on a query sample sized to about ``target_s`` host
+    seconds (between ``min_rows`` and ``max_rows`` queries when given)."""
     import numpy as np
 
     import oracle
@@ -135,6 +136,8 @@ def oracle_sample(Q, R, k, metrics, target_s, seed=12345, max_rows=None):
     nsamp = int(min(n, max(len(probe), target_s / max(per_query, 1e-9))))
     if max_rows:
         nsamp = min(nsamp, max_rows)
+    if min_rows:
+        nsamp = max(nsamp, min(n, min_rows))
     rows = np.sort(rng.choice(n, size=nsamp, replace=False))
     log(f"[bench] oracle sample: {nsamp} queries x {R.shape[0]} references x {len(metrics)} distances, "
         f"{threads} threads")
@@ -260,6 +263,13 @@ def bench_pairs(args):
 
 # -------------------------------------------------------------- precision
 def bench_precision(args):
+    """The default line: 2^20 references, 65536 queries, d = 128, k = 32,
+    1024-component mixture (sigma 0.1), both sets resident.  ``value`` is the
+    plain float32 search (float32 tiles on the matrix cores + 8 extra
+    candidates + exact float32 re-rank); the same line reports the BF16 form
+    (BF16 tiles, float32 accumulation, 32 extra candidates, exact float32
+    re-rank), its speedup, recall@32 and distance errors of both against the
+    FP64 oracle on a seeded query sample, and both kernels' rooflines."""
     import numpy as np
     import torch
 
@@ -272,58 +282,77 @@ def bench_precision(args):
     t0 = time.perf_counter()
     R = synthdata.gmm(m, d, p["comps"], p["sigma"], p["wid"], synthdata.ROLE_REFS, threads=th)
     Q = synthdata.gmm(n, d, p["comps"], p["sigma"], p["wid"], synthdata.ROLE_QUERIES, threads=th)
-    log(f"[bench] precision workload: n={n} m={m} d={d} k={k}, generated in {time.perf_counter() - t0:.1f} s")
+    log(f"[bench] workload gmm1m_d128: n={n} m={m} d={d} k={k}, generated in {time.perf_counter() - t0:.1f} s")
     Rd = torch.from_numpy(R).cuda()
     Qd = torch.from_numpy(Q).cuda()
-    refs16 = K.Refs(Rd, storage="bf16", keep_fp32_master=True)
     refs32 = K.Refs(Rd, storage="fp32")
+    refs16 = K.Refs(Rd, storage="bf16", keep_fp32_master=True)
     del Rd
-    out16 = (torch.empty((n, k), dtype=torch.float32, device="cuda"), torch.empty((n, k), dtype=torch.int32,
-                                                                                  device="cuda"))
-    out32 = (torch.empty_like(out16[0]), torch.empty_like(out16[1]))
+    out32 = (torch.empty((n, k), dtype=torch.float32, device="cuda"),
+             torch.empty((n, k), dtype=torch.int32, device="cuda"))
+    out16 = (torch.empty_like(out32[0]), torch.empty_like(out32[1]))
     s_extra = 32
-    sec16, kern16 = timed(K, torch, lambda: refs16.search(Qd, k, "l2", precision="bf16", s_extra=s_extra,
-                                                          out=out16), args.steps, args.warmup)
     sec32, kern32 = timed(K, torch, lambda: refs32.search(Qd, k, "l2", precision="fp32", out=out32),
                           args.steps, args.warmup)
+    sec16, kern16 = timed(K, torch, lambda: refs16.search(Qd, k, "l2", precision="bf16", s_extra=s_extra,
+                                                          out=out16), args.steps, args.warmup)
     pairs = float(n) * m
-    log(f"[bench] bf16+rerank {sec16 * 1e3:.2f} ms ({pairs / sec16:.4e} pairs/s), fp32 {sec32 * 1e3:.2f} ms "
-        f"({pairs / sec32:.4e} pairs/s)")
-    for tag, kt in (("bf16", kern16), ("fp32", kern32)):
+    log(f"[bench] fp32 {sec32 * 1e3:.2f} ms ({pairs / sec32:.4e} pairs/s), bf16+rerank {sec16 * 1e3:.2f} ms "
+        f"({pairs / sec16:.4e} pairs/s)")
+    for tag, kt in (("fp32", kern32), ("bf16", kern16)):
         for name, v in kt.items():
             log(f"[bench]   {tag} {name:16s} avg {v['avg_ms']:.4f} ms x {v['launches']}")
-    roof16 = kernel_roofline("fused_l2_bf16", kern16["fused_l2_bf16"]["avg_ms"] / 1e3, pairs, d)
     roof32 = kernel_roofline("fused_l2_f32", kern32["fused_l2_f32"]["avg_ms"] / 1e3, pairs, d)
+    roof16 = kernel_roofline("fused_l2_bf16", kern16["fused_l2_bf16"]["avg_ms"] / 1e3, pairs, d)
+    traffic = measured_traffic("gmm1m_d128")
+    for roof in (roof32, roof16):
+        roof["traffic"] = traffic.get(roof["kernel"])
+        if roof["traffic"] is not None:
+            roof["traffic_source"] = "profiles/fused_gmm1m_d128_traffic.json (rocprofv3 FETCH_SIZE + WRITE_SIZE)"
     result = {
-        "metric": "query-ref pairs/sec",
-        "value": pairs / sec16,
+        "metric": "query-ref pairs/sec + recall@k vs FP64 oracle",
+        "value": pairs / sec32,
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec16 * 1e3,
+        "ms_per_step": sec32 * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16 tiles, f32 accumulate + f32 re-rank",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "gmm1m_d128", "n": n, "m": m, "d": d, "k": k, "s_extra": s_extra,
-                   "data": f"{p['comps']}-component isotropic Gaussian mixture, sigma {p['sigma']}"},
-        "fp32": {"value": pairs / sec32, "ms_per_step": sec32 * 1e3, "roofline": roof32},
-        "speedup_vs_fp32": sec32 / sec16,
-        "roofline": roof16,
-        "kernels": {"bf16": kern16, "fp32": kern32},
+        "config": {"workload": "gmm1m_d128", "n": n, "m": m, "d": d, "k": k, "distance": "l2",
+                   "data": f"{p['comps']}-component isotropic Gaussian mixture, sigma {p['sigma']}",
+                   "resident": "both reference sets prepared once (float32; bf16 + float32 master)"},
+        "roofline": roof32,
+        "bf16": {"value": pairs / sec16, "unit": "pairs/s", "ms_per_step": sec16 * 1e3, "s_extra": s_extra,
+                 "dtype": "bf16 tiles, f32 accumulate + f32 re-rank", "roofline": roof16,
+                 "speedup_vs_fp32": sec32 / sec16},
+        "kernels": {"fp32": kern32, "bf16": kern16},
     }
     if not args.no_cpu_baseline:
-        from oracle.check import compare
+        from oracle.check import compare, recall_ci
 
-        rows, refs, cpu_s, threads = oracle_sample(Q, R, k, ["l2"], args.cpu_seconds, max_rows=512)
-        rep16 = compare(Q, R, k, "l2", out16[0].cpu().numpy(), out16[1].cpu().numpy(), tol=1e-5, ref=refs["l2"],
-                        rows=rows)
+        rows, refs, cpu_s, threads = oracle_sample(Q, R, k, ["l2"], args.cpu_seconds, max_rows=args.recall_queries,
+                                                   min_rows=args.recall_queries)
         rep32 = compare(Q, R, k, "l2", out32[0].cpu().numpy(), out32[1].cpu().numpy(), tol=1e-5, ref=refs["l2"],
                         rows=rows)
-        result["parity_vs_oracle"] = {"bf16": parity_summary(rep16), "fp32": parity_summary(rep32)}
-        result["recall_at_k"] = {"bf16": rep16["recall"], "fp32": rep32["recall"]}
+        rep16 = compare(Q, R, k, "l2", out16[0].cpu().numpy(), out16[1].cpu().numpy(), tol=1e-5, ref=refs["l2"],
+                        rows=rows)
+        slots = len(rows) * k
+        for tag, rep in (("fp32", rep32), ("bf16", rep16)):
+            lo, hi = recall_ci(rep["recall"], slots)
+            rep["recall_ci95"] = [lo, hi]
+            log(f"[bench] {tag}: recall@{k} {rep['recall']:.6f} (95% CI [{lo:.6f}, {hi:.6f}], {slots} slots), "
+                f"max rel err {rep['max_rel_err']:.2e} (hits {rep['max_rel_err_hits']:.2e}), "
+                f"tie-aware check {'ok' if rep['ok'] else 'FAILED'}")
+        result["parity_vs_oracle"] = {"fp32": parity_summary(rep32), "bf16": parity_summary(rep16)}
+        result["recall_at_k"] = {"fp32": rep32["recall"], "bf16": rep16["recall"]}
+        result["recall_ci95"] = {"fp32": rep32["recall_ci95"], "bf16": rep16["recall_ci95"],
+                                 "method": "Wilson score interval", "slots": slots}
+        result["bf16"]["recall_at_k"] = rep16["recall"]
+        result["bf16"]["max_rel_err_hits"] = rep16["max_rel_err_hits"]
         result["cpu_baseline"] = {
             "value": float(len(rows)) * m / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(rows)} seeded queries of {n} against all {m} references, Euclidean, FP64 brute force "
@@ -773,11 +802,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--mode", default="pairs", choices=["pairs", "precision", "batched", "serve", "copy", "entropy",
+    ap.add_argument("--mode", default="precision", choices=["pairs", "precision", "batched", "serve", "copy", "entropy",
                                                       "mahalanobis", "classify", "table"])
     ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
+    ap.add_argument("--recall-queries", type=int, default=2048,
+                    help="precision mode: seeded queries checked against the FP64 oracle (recall@k sample)")
     ap.add_argument("--instances", type=int, default=512, help="batched mode: number of instances")
     ap.add_argument("--requests", type=int, default=10000, help="serve mode: requests per trace")
     ap.add_argument("--sizes", default="uniform", choices=["uniform", "loguniform"],
@@ -793,7 +824,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
               "across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"pairs": (50, 5), "precision": (5, 1), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3), "table": (5, 1)}
+    defaults = {"pairs": (50, 5), "precision": (10, 2), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3), "table": (5, 1)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:

@@ -67,10 +67,13 @@ enum knn_status {
 
 typedef struct knn_refs_s* knn_refs_t; /* opaque, owned by the library */
 
-/* Library version, major*10000 + minor*100 + patch. */
+/* Library version, major*10000 + minor*100 + patch.  (Library metadata: no
+ * passage of the paper defines it.) */
 int knn_version(void);
 
-/* Thread-local text of the last error on this thread ("" if none). */
+/* Thread-local text of the last error on this thread ("" if none).  The
+ * returned pointer stays valid until the next library call on this thread.
+ * (Error reporting of the library: no passage of the paper defines it.) */
 const char* knn_last_error(void);
 
 /*
@@ -165,15 +168,24 @@ int knn_entropy(const float* Y, int64_t n, int32_t d, int32_t k, double* out, vo
 int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage,
                     int32_t keep_fp32_master, void* stream, knn_refs_t* out);
 
-/* Release a handle and its device memory (waits for the device first). */
+/* knn_destroy_refs -- release a reference set prepared for the Section 2.1
+ * search.  Waits for the work enqueued on the handle's creation stream and
+ * for every search of the handle the library enqueued on other streams, then
+ * frees the handle's device memory; work of other handles and streams is
+ * not waited for.  Searches of the handle enqueued by the caller must not be
+ * in flight on other streams unless they were enqueued through this library
+ * (the library records their completion).
+ * Errors: KNN_ERR_INVALID (not a live handle), KNN_ERR_DEVICE. */
 int knn_destroy_refs(knn_refs_t refs);
 
-/* Shape of a handle: any output pointer may be NULL. */
+/* Shape of a handle: any output pointer may be NULL.  (Introspection: no
+ * passage of the paper defines it.) */
 int knn_refs_info(knn_refs_t refs, int64_t* m, int32_t* d, int32_t* storage,
                   int32_t* has_fp32_master);
 
 /*
- * knn_search_refs -- brute force against a resident set.
+ * knn_search_refs -- the brute force of Section 2.1 (every query-reference
+ * distance, the k smallest per query) against a resident set.
  *   Q [n][d] device float32, same d as the set.
  *   precision: enum knn_precision of the distance tiles; KNN_FP32 needs
  *     float32 rows (storage KNN_FP32), KNN_BF16 / KNN_FP16 need rows stored
@@ -193,6 +205,9 @@ int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32
 
 /*
  * Batched search: many independent instances of the Section 2.1 problem
+ * (the paper notes that every distance and every per-query selection is
+ * independent of the others, which is what lets instances share launches;
+ * the batching itself is this library's, no passage defines it)
  * (each a query set against a resident reference set, with its own n, d, k
  * and metric), scored in a handful of launches.
  *   knn_problem_t: one instance.  Q [n][d] device float32 (d of the set),
@@ -239,7 +254,12 @@ int knn_search_batched(const knn_problem_t* probs, int32_t count, int32_t precis
 
 /*
  * Serving engine: resident reference sets answer requests that arrive from
- * host memory while others are on the device (continuous batching).
+ * host memory while others are on the device (continuous batching).  Each
+ * request is the Section 2.1 problem (its queries against one resident set,
+ * Euclidean); the paper's timings were dominated by host-device copies
+ * (Section 3), which is why the sets stay resident.  The engine (admission,
+ * batching, streams) is this library's own: no passage of the paper defines
+ * it.
  *   knn_server_create(sets, nsets, cfg, out): `sets` are resident sets (all
  *     stored in cfg->precision); the engine thread owns one device arena of
  *     cfg->mem_budget bytes (all request memory: queries, outputs, search
@@ -309,7 +329,8 @@ int knn_server_stats(knn_server_t srv, knn_server_stats_t* out);
 int knn_server_destroy(knn_server_t srv);
 
 /*
- * Kernel timing with HIP events (a measurement aid, not part of the method).
+ * Kernel timing with HIP events (a measurement aid, not part of the method:
+ * no passage of the paper defines it).
  *   knn_timing_enable(1): every later launch of the library records a start
  *     and a stop event on the stream it is launched on; (0) stops recording.
  *   knn_timing_read(name, total_ms, launches): waits for the recorded events,

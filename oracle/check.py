@@ -11,7 +11,12 @@ relative tolerance.  A result (dist, idx) passes when, for every rank r < k:
   tol * D*[i,r] of D*[i,r].  The returned index therefore equals the oracle's
   one unless another reference is within the tolerance at that rank: that
   allows reorderings inside near-tie groups and swaps across the k boundary,
-  and nothing else.
+  and nothing else;
+* pairing:         the returned distance is the distance to the returned
+  reference: |dist[i,r] - D64(q_i, r_idx[i,r])| <= tol * D64(q_i, r_idx[i,r]).
+  For the float32 path it follows from T1 and T2 up to a factor 2; for the
+  low-precision forms, where T1 binds only the hits, it is what ties every
+  returned distance (hit or miss) to its index.
 
 Recall for the low-precision forms:
 * strict recall@k = mean_i |S_i intersect S*_i| / k (S* = oracle's top-k index set);
@@ -42,6 +47,8 @@ def compare(Q, R, k, metric, dist, idx, tol=1e-5, ref=None, rows=None):
     if ref is None:
         ref = knn(Q[rows], R, k, metric)
     Ds, Is = ref
+    if Ds.shape != (rows.size, k) or Is.shape != (rows.size, k) or dist.shape != (rows.size, k):
+        raise ValueError(f"shapes differ: oracle {Ds.shape}, result {dist.shape}, {rows.size} rows x k = {k}")
     m = R.shape[0]
     nq = rows.size
     rep = {"queries": int(nq), "k": int(k), "tol": tol}
@@ -52,10 +59,12 @@ def compare(Q, R, k, metric, dist, idx, tol=1e-5, ref=None, rows=None):
     safe_idx = np.where(in_range, idx, 0)
     d64 = pair_dist(Q, R, np.repeat(rows, k), safe_idx.ravel(), metric).reshape(nq, k)
     lim = tol * Ds
-    bad_dist = np.abs(dist - Ds) > lim
+    bad_dist = ~(np.abs(dist - Ds) <= lim)  # NaN fails
     bad_idx = (np.abs(d64 - Ds) > lim) | ~in_range
+    bad_pair = ~(np.abs(dist - d64) <= tol * d64) | ~in_range
     rep["bad_dist"] = int(bad_dist.sum())
     rep["bad_idx"] = int(bad_idx.sum())
+    rep["bad_pair"] = int(bad_pair.sum())
     pos = Ds > 0
     rel = np.zeros_like(Ds)
     rel[pos] = np.abs(dist[pos] - Ds[pos]) / Ds[pos]
@@ -72,8 +81,10 @@ def compare(Q, R, k, metric, dist, idx, tol=1e-5, ref=None, rows=None):
     relh[posh] = np.abs(dist[posh] - d64[posh]) / d64[posh]
     relh[~posh] = np.where(dist[~posh] == 0, 0.0, np.inf)
     rep["max_rel_err_hits"] = float(relh[hits].max()) if hits.any() else 0.0
+    rep["max_rel_err_pair"] = float(relh.max()) if relh.size else 0.0
     rep["exact_idx_match"] = float(np.mean(idx == Is))
-    rep["ok"] = rep["bad_index_rows"] == 0 and rep["bad_dist"] == 0 and rep["bad_idx"] == 0
+    rep["ok"] = (rep["bad_index_rows"] == 0 and rep["bad_dist"] == 0 and rep["bad_idx"] == 0
+                 and rep["bad_pair"] == 0)
     return rep
 
 

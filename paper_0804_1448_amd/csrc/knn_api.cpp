@@ -48,40 +48,68 @@ int hip_fail(hipError_t e, const char* what) {
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 int64_t ceil_div(int64_t x, int64_t a) { return (x + a - 1) / a; }
 
+// ------------------------------------------------------ device allocation
+// Every device allocation of the library goes through dev_alloc, which also
+// carries the allocation-failure test hook: with KNN_FAIL_ALLOC=N in the
+// environment, the N-th allocation from then on (1 = the next) fails as if
+// the device were out of memory, and the variable is cleared.
+int dev_alloc(void** out, size_t bytes, const char* what) {
+  *out = nullptr;
+  static std::mutex hook_mutex;
+  {
+    std::lock_guard<std::mutex> lock(hook_mutex);
+    const char* v = getenv("KNN_FAIL_ALLOC");
+    if (v && *v) {
+      const long left = atol(v);
+      if (left <= 1) {
+        unsetenv("KNN_FAIL_ALLOC");
+        return fail(KNN_ERR_OOM, "%s: injected allocation failure (KNN_FAIL_ALLOC)", what);
+      }
+      char buf[32];
+      snprintf(buf, sizeof buf, "%ld", left - 1);
+      setenv("KNN_FAIL_ALLOC", buf, 1);
+    }
+  }
+  const hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return hip_fail(e, what);
+  }
+  return KNN_OK;
+}
+
 // --------------------------------------------------- per-stream workspace
-// A grow-only device buffer per (device, stream).  Growing frees the old
-// buffer; hipFree waits for the device, so work still queued on the old
-// buffer completes first.
-struct Workspace {
-  void* ptr = nullptr;
-  size_t size = 0;
-};
+// A grow-only device buffer per (device, stream).  A search holds the
+// buffer's lock from the moment it takes the buffer until its last launch is
+// enqueued, so the launches of two searches on one stream never interleave
+// (stream order then keeps one search's kernels from overwriting the
+// other's data).  A buffer that grows is released only after the work
+// already enqueued on its stream has finished.
+int workspace_grow(Workspace& w, hipStream_t stream, size_t bytes) {
+  if (w.size >= bytes) return KNN_OK;
+  if (w.ptr) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.size = 0;
+    if (e != hipSuccess) return hip_fail(e, "releasing the workspace");
+  }
+  const size_t want = std::max(bytes, (size_t)1 << 20);
+  int st = dev_alloc(&w.ptr, want, "workspace allocation");
+  if (st != KNN_OK) return st;
+  w.size = want;
+  return KNN_OK;
+}
 
 std::mutex g_ws_mutex;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 
-int workspace(hipStream_t stream, size_t bytes, void** out) {
+Workspace* workspace_of(hipStream_t stream) {
   int dev = 0;
-  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lock(g_ws_mutex);
-  Workspace& w = g_ws[{dev, stream}];
-  if (w.size < bytes) {
-    if (w.ptr) {
-      hipError_t e = hipFree(w.ptr);
-      w.ptr = nullptr;
-      w.size = 0;
-      if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
-    }
-    size_t want = std::max(bytes, (size_t)1 << 20);
-    hipError_t e = hipMalloc(&w.ptr, want);
-    if (e != hipSuccess) {
-      w.ptr = nullptr;
-      return hip_fail(e, "hipMalloc(workspace)");
-    }
-    w.size = want;
-  }
-  *out = w.ptr;
-  return KNN_OK;
+  return &g_ws[{dev, stream}];  // std::map keeps element addresses stable
 }
 
 // ---------------------------------------------------------- kernel timing
@@ -94,6 +122,7 @@ struct TimingRecord {
 
 std::mutex g_tm_mutex;
 bool g_tm_enabled = false;
+thread_local bool g_tm_suppress = false;
 std::vector<hipEvent_t> g_tm_pool;
 std::vector<TimingRecord> g_tm_pending;
 std::map<std::string, std::pair<double, int64_t>> g_tm_totals;
@@ -113,6 +142,7 @@ hipEvent_t tm_event() {
 class TimedLaunch {
  public:
   TimedLaunch(const char* name, hipStream_t s) : stream_(s) {
+    if (g_tm_suppress) return;
     std::lock_guard<std::mutex> lock(g_tm_mutex);
     if (!g_tm_enabled) return;
     start_ = tm_event();
@@ -505,10 +535,12 @@ int run_search(const SearchArgs& a) {
   size_t need = 0;
   int st = run_search_ws(a, nullptr, 0, &need);
   if (st != KNN_OK) return st;
-  void* ws = nullptr;
-  st = workspace(a.stream, need, &ws);
+  Workspace* w = workspace_of(a.stream);
+  if (!w) return fail(KNN_ERR_DEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(w->mu);
+  st = workspace_grow(*w, a.stream, need);
   if (st != KNN_OK) return st;
-  return run_search_ws(a, ws, need, nullptr);
+  return run_search_ws(a, w->ptr, need, nullptr);
 }
 
 int check_common(int64_t n, int64_t m, int32_t d, int32_t k, int32_t metric) {
@@ -530,6 +562,31 @@ int tile_kind(int metric, int precision) {
 }
 
 int default_extra(int precision) { return precision == KNN_FP32 ? 8 : 32; }
+
+int one_shot_args(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, int32_t k, int32_t metric,
+                  float* dist, int32_t* idx, hipStream_t stream, SearchArgs* out) {
+  int st = check_common(n, m, d, k, metric);
+  if (st != KNN_OK || n == 0) return st;
+  if ((st = check_ptr(Q, "Q")) || (st = check_ptr(R, "R")) || (st = check_ptr(dist, "dist")) ||
+      (st = check_ptr(idx, "idx")))
+    return st;
+  SearchArgs& a = *out;
+  a = SearchArgs{};
+  a.Q = Q;
+  a.n = n;
+  a.d = d;
+  a.m = m;
+  a.R32 = R;
+  a.k = k;
+  a.kprime = (int)std::min<int64_t>(m, (int64_t)k + default_extra(KNN_FP32));
+  a.metric = metric;
+  a.kind = tile_kind(metric, KNN_FP32);
+  a.dist = dist;
+  a.idx = idx;
+  a.stream = stream;
+  return KNN_OK;
+}
+
 
 bool valid_refs(knn_refs_t r) { return r && r->magic == 0x6b6e6e52u; }
 
@@ -587,7 +644,44 @@ void free_refs(knn_refs_s* h) {
   (void)hipFree(h->rhalf);
   (void)hipFree(h->centre);
   (void)hipFree(h->master);
+  (void)hipFree(h->flag);
+  h->rows = nullptr;
+  h->rhalf = h->centre = h->master = nullptr;
+  h->flag = nullptr;
+  for (auto& u : h->uses) (void)hipEventDestroy(u.second);
+  h->uses.clear();
 }
+
+int record_use(std::mutex& mu, std::vector<std::pair<hipStream_t, hipEvent_t>>& uses, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return KNN_OK;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& u : uses)
+    if (u.first == s) {
+      HIP_TRY(hipEventRecord(u.second, s), "hipEventRecord(use)");
+      return KNN_OK;
+    }
+  hipEvent_t e = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate(use)");
+  uses.push_back({s, e});
+  HIP_TRY(hipEventRecord(e, s), "hipEventRecord(use)");
+  return KNN_OK;
+}
+
+// wait for and release every recorded use; returns the first error
+hipError_t wait_uses(std::mutex& mu, std::vector<std::pair<hipStream_t, hipEvent_t>>& uses) {
+  std::lock_guard<std::mutex> lock(mu);
+  hipError_t e = hipSuccess;
+  for (auto& u : uses) {
+    const hipError_t e2 = hipEventSynchronize(u.second);
+    if (e == hipSuccess) e = e2;
+    (void)hipEventDestroy(u.second);
+  }
+  uses.clear();
+  return e;
+}
+
+int note_use(knn_refs_s* h, hipStream_t s) { return record_use(h->use_mu, h->uses, s); }
 
 }  // namespace knn::host
 
@@ -599,25 +693,9 @@ const char* knn_last_error(void) { return g_last_error.c_str(); }
 
 int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, int32_t k, int32_t metric,
                float* dist, int32_t* idx, void* stream) {
-  int st = check_common(n, m, d, k, metric);
-  if (st != KNN_OK) return st;
-  if (n == 0) return KNN_OK;
-  if ((st = check_ptr(Q, "Q")) || (st = check_ptr(R, "R")) || (st = check_ptr(dist, "dist")) ||
-      (st = check_ptr(idx, "idx")))
-    return st;
   SearchArgs a{};
-  a.Q = Q;
-  a.n = n;
-  a.d = d;
-  a.m = m;
-  a.R32 = R;
-  a.k = k;
-  a.kprime = (int)std::min<int64_t>(m, (int64_t)k + default_extra(KNN_FP32));
-  a.metric = metric;
-  a.kind = tile_kind(metric, KNN_FP32);
-  a.dist = dist;
-  a.idx = idx;
-  a.stream = (hipStream_t)stream;
+  const int st = one_shot_args(Q, n, R, m, d, k, metric, dist, idx, (hipStream_t)stream, &a);
+  if (st != KNN_OK || n == 0) return st;
   return run_search(a);
 }
 
@@ -719,7 +797,7 @@ int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage, int32
   int st = check_ptr(R, "R");
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  knn_refs_s* h = new (std::nothrow) knn_refs_s;
+  std::unique_ptr<knn_refs_s> h(new (std::nothrow) knn_refs_s);
   if (!h) return fail(KNN_ERR_OOM, "host allocation of the handle failed");
   h->m = m;
   h->d = d;
@@ -729,30 +807,49 @@ int knn_create_refs(const float* R, int64_t m, int32_t d, int32_t storage, int32
   h->dp32 = padded_dim(TILE_L1_F32, d);
   const int es = storage == KNN_FP32 ? 4 : 2;
   const bool master = storage == KNN_FP32 || keep_fp32_master;
-  hipError_t e = hipGetDevice(&h->device);
-  if (e == hipSuccess) e = hipMalloc(&h->rows, (size_t)m * h->dp * es);
-  if (e == hipSuccess) e = hipMalloc((void**)&h->rhalf, (size_t)m * 4);
-  if (e == hipSuccess && master) e = hipMalloc((void**)&h->master, (size_t)m * h->dp32 * 4);
-  if (e == hipSuccess && master) e = hipMalloc((void**)&h->centre, (size_t)d * 4);
+  const bool narrow = storage != KNN_FP32;
+  auto cleanup = [&](int rc) {
+    free_refs(h.get());
+    return rc;
+  };
+  HIP_TRY(hipGetDevice(&h->device), "hipGetDevice");
+  if ((st = dev_alloc(&h->rows, (size_t)m * h->dp * es, "reference rows")) ||
+      (st = dev_alloc((void**)&h->rhalf, (size_t)m * 4, "reference norms")) ||
+      (master && (st = dev_alloc((void**)&h->master, (size_t)m * h->dp32 * 4, "float32 master rows"))) ||
+      (master && (st = dev_alloc((void**)&h->centre, (size_t)d * 4, "centre"))) ||
+      (narrow && (st = dev_alloc((void**)&h->flag, 256, "range flag"))))
+    return cleanup(st);
+  // 16-bit storage: the flag is set when a row value rounds to infinity
+  unsigned* overflow = h->flag;
+  float* centre = h->centre;
+  hipError_t e = hipSuccess;
+  if (overflow) e = hipMemsetAsync(overflow, 0, 4, s);
   // rows are translated by the centre only when a float32 master keeps the
   // untranslated values for the re-rank
-  if (e == hipSuccess && master) e = launch_centre(R, m, d, d, h->centre, s);
-  if (e == hipSuccess) e = launch_prep_rows(R, m, d, d, h->centre, h->rows, h->dp, elem_of_kind(kind), h->rhalf, s);
+  if (e == hipSuccess && master) e = launch_centre(R, m, d, d, centre, s);
+  if (e == hipSuccess)
+    e = launch_prep_rows(R, m, d, d, centre, h->rows, h->dp, elem_of_kind(kind), h->rhalf, s, overflow);
   if (e == hipSuccess && master) e = launch_prep_rows(R, m, d, d, nullptr, h->master, h->dp32, ELEM_F32, nullptr, s);
-  if (e != hipSuccess) {
-    int rc = hip_fail(e, "knn_create_refs");
-    free_refs(h);
-    delete h;
-    return rc;
+  if (e != hipSuccess) return cleanup(hip_fail(e, "knn_create_refs"));
+  if (overflow) {
+    // the range check needs the preparation's result: wait for this stream
+    unsigned flag = 0;
+    e = hipMemcpyAsync(&flag, overflow, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "knn_create_refs range check"));
+    if (flag)
+      return cleanup(fail(KNN_ERR_UNSUPPORTED, "a reference value%s exceeds the %s range",
+                          master ? " minus the set's centre" : "", storage == KNN_FP16 ? "float16 (65504)" : "bfloat16"));
   }
-  *out = h;
+  if ((st = note_use(h.get(), s)) != KNN_OK) return cleanup(st);
+  *out = h.release();
   return KNN_OK;
 }
 
 int knn_destroy_refs(knn_refs_t refs) {
   if (!valid_refs(refs)) return fail(KNN_ERR_INVALID, "not a live reference-set handle");
   refs->magic = 0;
-  hipError_t e = hipDeviceSynchronize();
+  const hipError_t e = wait_uses(refs->use_mu, refs->uses);
   free_refs(refs);
   delete refs;
   if (e != hipSuccess) return hip_fail(e, "knn_destroy_refs");
@@ -777,7 +874,9 @@ int knn_search_refs(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32
   SearchArgs a;
   int st = refs_search_args(refs, Q, n, k, metric, precision, s_extra, dist, idx, (hipStream_t)stream, &a);
   if (st != KNN_OK) return st;
-  return run_search(a);
+  st = run_search(a);
+  if (st != KNN_OK) return st;
+  return note_use(refs, (hipStream_t)stream);
 }
 
 int knn_timing_enable(int32_t enable) {
@@ -925,6 +1024,8 @@ struct knn_batch_s {
   int nfitems = 0, keys_max = 0, p_max = 1, kprime_max = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::mutex use_mu;  // completion of every run, one event per stream
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 namespace knn::host {
@@ -1078,6 +1179,8 @@ int batch_tune(knn_batch_s& b, hipStream_t s) {
 }
 
 void free_batch(knn_batch_s* b) {
+  for (auto& u : b->uses) (void)hipEventDestroy(u.second);
+  b->uses.clear();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->ws) (void)hipFree(b->ws);
@@ -1200,11 +1303,7 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
   for (BatchInst& in : b->inst) nf += ceil_div(in.prob.n, kFinalWaves);
   b->fitems_off = take((size_t)nf * sizeof(FinalItem));
   b->ws_size = std::max<size_t>(off, 256);
-  hipError_t e = hipMalloc(&b->ws, b->ws_size);
-  if (e != hipSuccess) {
-    b->ws = nullptr;
-    return hip_fail(e, "hipMalloc(batch workspace)");
-  }
+  if (int st0 = dev_alloc(&b->ws, b->ws_size, "batch workspace")) return st0;
   std::unique_ptr<knn_batch_s, void (*)(knn_batch_s*)> guard(b.get(), [](knn_batch_s* p) { free_batch(p); });
   unsigned char* w = (unsigned char*)b->ws;
   // ---- descriptors: query preparation, fused instances and items, finalize
@@ -1300,9 +1399,11 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
   return KNN_OK;
 }
 
-int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream) {
-  if (!valid_batch(batch)) return fail(KNN_ERR_INVALID, "not a live batch handle");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace knn::host {
+
+int batch_run(knn_batch_t batch, int32_t use_graph, hipStream_t s) {
   if ((batch->flags & KNN_BATCH_TUNE)) {
     int st = batch_tune(*batch, s);
     if (st != KNN_OK) return st;
@@ -1357,10 +1458,21 @@ int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream) {
   return KNN_OK;
 }
 
+}  // namespace knn::host
+
+extern "C" {
+
+int knn_batch_run(knn_batch_t batch, int32_t use_graph, void* stream) {
+  if (!valid_batch(batch)) return fail(KNN_ERR_INVALID, "not a live batch handle");
+  const int st = batch_run(batch, use_graph, (hipStream_t)stream);
+  if (st != KNN_OK) return st;
+  return record_use(batch->use_mu, batch->uses, (hipStream_t)stream);
+}
+
 int knn_batch_destroy(knn_batch_t batch) {
   if (!valid_batch(batch)) return fail(KNN_ERR_INVALID, "not a live batch handle");
   batch->magic = 0;
-  hipError_t e = hipDeviceSynchronize();
+  const hipError_t e = wait_uses(batch->use_mu, batch->uses);
   free_batch(batch);
   delete batch;
   if (e != hipSuccess) return hip_fail(e, "knn_batch_destroy");

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "knn.h"
 #include "knn_internal.h"
 
@@ -27,8 +31,13 @@ struct knn_refs_s {
   float* rhalf = nullptr;
   float* centre = nullptr;
   float* master = nullptr;
+  unsigned* flag = nullptr;  // 16-bit storage: range check of the rounded rows
   int device = 0;
   uint32_t magic = 0x6b6e6e52u;
+  // completion of the handle's creation and of every search of it the
+  // library enqueued, one event per stream (knn_destroy_refs waits for them)
+  std::mutex use_mu;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
 };
 
 namespace knn::host {
@@ -59,6 +68,20 @@ struct SearchArgs {
 int fail(int status, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 
+// Device allocation with the KNN_FAIL_ALLOC test hook (see knn_api.cpp).
+int dev_alloc(void** out, size_t bytes, const char* what);
+
+// Record on `stream` that work using `refs` has been enqueued there.
+int note_use(knn_refs_s* refs, hipStream_t stream);
+
+// A grow-only per-stream device buffer; `mu` is held by a search from taking
+// the buffer to its last launch.
+struct Workspace {
+  std::mutex mu;
+  void* ptr = nullptr;
+  size_t size = 0;
+};
+
 #define HIP_TRY(expr, what)                            \
   do {                                                 \
     hipError_t e_ = (expr);                            \
@@ -70,6 +93,15 @@ int check_common(int64_t n, int64_t m, int32_t d, int32_t k, int32_t metric);
 // Fill `a` for a search of `refs` (argument checks included; returns a status).
 int refs_search_args(knn_refs_t refs, const float* Q, int64_t n, int32_t k, int32_t metric, int32_t precision,
                      int32_t s_extra, float* dist, int32_t* idx, hipStream_t stream, SearchArgs* a);
+
+// Check the arguments of a one-shot float32 search (knn_search) and fill `a`;
+// n == 0 returns KNN_OK with `a` untouched.
+int one_shot_args(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, int32_t k, int32_t metric,
+                  float* dist, int32_t* idx, hipStream_t stream, SearchArgs* a);
+
+// Set on a thread to keep kernel timing from recording events (which may
+// allocate) for the launches it makes.
+extern thread_local bool g_tm_suppress;
 
 // Run one search in the caller's workspace; with ws == nullptr only the
 // needed size is stored in *need.

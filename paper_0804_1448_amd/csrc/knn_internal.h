@@ -139,8 +139,10 @@ constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
 
 // Launchers (knn_kernels.hip).  All enqueue on `stream` and return the HIP
 // status of the launch.
+// overflow (16-bit elements only, may be NULL): set to 1 when a finite value
+// rounds to infinity in the element type
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst,
-                            int ldd, int elem, float* rhalf, hipStream_t stream);
+                            int ldd, int elem, float* rhalf, hipStream_t stream, unsigned* overflow = nullptr);
 // float32 rows in the 32-row tile layout [i / 32][t / 4][i % 32][t % 4]
 // (ldd a multiple of 4; dst holds round_up(rows, 32) rows)
 hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds, const float* centre, float* dst,

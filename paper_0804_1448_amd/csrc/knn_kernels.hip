@@ -62,7 +62,7 @@ template <int E, bool TILED = false>
 __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict__ src, int64_t rows, int d,
                                                         int lds, const float* __restrict__ centre,
                                                         void* __restrict__ dst, int ldd,
-                                                        float* __restrict__ rhalf) {
+                                                        float* __restrict__ rhalf, unsigned* __restrict__ overflow) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= rows) return;
@@ -79,10 +79,12 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
       uint16_t b = f32_to_bf16_rne(v);
       ((uint16_t*)dst)[row * ldd + t] = b;
       stored = bf16_to_f32(b);
+      if (overflow && (b & 0x7fffu) == 0x7f80u) *overflow = 1u;  // finite input rounded to infinity
     } else {
       uint16_t b = f32_to_f16_rne(v);
       ((uint16_t*)dst)[row * ldd + t] = b;
       stored = f16_to_f32(b);
+      if (overflow && (b & 0x7fffu) == 0x7c00u) *overflow = 1u;  // |v| beyond the float16 range
     }
     acc += stored * stored;
   }
@@ -97,21 +99,23 @@ hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds
                                   int ldd, float* rhalf, hipStream_t stream) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL((prep_rows_kernel<ELEM_F32, true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, src,
-                     rows, d, lds, centre, (void*)dst, ldd, rhalf);
+                     rows, d, lds, centre, (void*)dst, ldd, rhalf, (unsigned*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst, int ldd,
-                            int elem, float* rhalf, hipStream_t stream) {
+                            int elem, float* rhalf, hipStream_t stream, unsigned* overflow) {
   if (rows <= 0) return hipSuccess;
   dim3 grid((unsigned)((rows + 3) / 4)), block(256);
   if (elem == ELEM_F32)
-    hipLaunchKernelGGL(prep_rows_kernel<ELEM_F32>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf);
+    hipLaunchKernelGGL(prep_rows_kernel<ELEM_F32>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf,
+                       (unsigned*)nullptr);
   else if (elem == ELEM_BF16)
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_BF16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd,
-                       rhalf);
+                       rhalf, overflow);
   else
-    hipLaunchKernelGGL(prep_rows_kernel<ELEM_F16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf);
+    hipLaunchKernelGGL(prep_rows_kernel<ELEM_F16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf,
+                       overflow);
   return hipGetLastError();
 }
 

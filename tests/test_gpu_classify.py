@@ -74,6 +74,12 @@ def test_votes_match_oracle(K, n, m, d, k, comps):
     assert rep["ok"], rep
     expect = np.array([C.vote(lab[row]) for row in idx])
     assert np.array_equal(pred, expect)
-    # and against the oracle's own neighbour sets wherever those agree
-    oracle_pred = C.classify(Q, R, lab, k)
-    assert np.mean(pred == oracle_pred) >= 0.99
+    # and exactly the oracle's own vote wherever the returned neighbours are the
+    # oracle's (elsewhere they differ only inside near-tie groups, checked above)
+    import oracle
+
+    _, oidx = oracle.knn(Q, R, k, "l2")
+    same = np.all(idx == oidx, axis=1)
+    oracle_pred = np.array([C.vote(lab[row]) for row in oidx])
+    assert same.mean() >= 0.9, same.mean()
+    assert np.array_equal(pred[same], oracle_pred[same])

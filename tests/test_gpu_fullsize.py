@@ -90,7 +90,7 @@ def test_precision_form_full_size(K, precision_sets, prec):
     rep = compare(s["Q"], s["R"], s["k"], "l2", dist, idx, tol=TOL, ref=s["ref"], rows=s["rows"])
     assert rep["bad_index_rows"] == 0, rep
     assert rep["recall"] >= 0.999, rep
-    assert rep["max_rel_err_hits"] <= TOL, rep
+    assert rep["max_rel_err_hits"] <= TOL and rep["bad_pair"] == 0 and rep["bad_index_rows"] == 0, rep
     assert np.all(np.diff(dist[s["rows"]], axis=1) >= 0)
 
 
@@ -142,7 +142,7 @@ def test_batched_form_full_size(K):
             dist, idx = outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy()
             rep = compare(Q, R, k, "l2", dist, idx, tol=TOL, ref=oracle.knn(Q[rows], R, k, "l2"), rows=rows)
             assert rep["bad_index_rows"] == 0, (i, rep)
-            assert rep["max_rel_err_hits"] <= TOL, (i, rep)
+            assert rep["max_rel_err_hits"] <= TOL and rep["bad_pair"] == 0, (i, rep)
             assert np.all(np.diff(dist[rows], axis=1) >= 0)
             hits += rep["recall"] * len(rows) * k
             total += len(rows) * k
@@ -195,7 +195,7 @@ def test_serving_form_full_size(K):
                 rows = np.arange(min(n, 8))
                 rep = compare(Q, canon[s], k, "l2", gd, gi, tol=TOL,
                               ref=oracle.knn(Q[rows], canon[s], k, "l2", threads=th), rows=rows)
-                assert rep["bad_index_rows"] == 0 and rep["max_rel_err_hits"] <= TOL, (j, rep)
+                assert rep["bad_index_rows"] == 0 and rep["bad_pair"] == 0 and rep["max_rel_err_hits"] <= TOL, (j, rep)
                 recall_num += rep["recall"] * len(rows)
                 recall_den += len(rows)
         assert recall_num / recall_den >= 0.999, recall_num / recall_den

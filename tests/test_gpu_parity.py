@@ -207,7 +207,7 @@ def test_low_precision_recall(K, prec, offset):
     rep = compare(Q, R, 32, "l2", dist, idx, tol=TOL)
     assert rep["bad_index_rows"] == 0
     assert rep["recall"] >= 0.999, rep
-    assert rep["max_rel_err_hits"] <= TOL, rep
+    assert rep["max_rel_err_hits"] <= TOL and rep["bad_pair"] == 0 and rep["bad_index_rows"] == 0, rep
     assert np.all(np.diff(dist, axis=1) >= 0)
 
 

@@ -56,7 +56,7 @@ def check(Q, R, k, dist, idx, min_recall=0.999):
     rep = compare(Q, R, k, "l2", dist, idx, tol=TOL)
     assert rep["bad_index_rows"] == 0, rep
     assert rep["recall"] >= min_recall, rep
-    assert rep["max_rel_err_hits"] <= TOL, rep
+    assert rep["max_rel_err_hits"] <= TOL and rep["bad_pair"] == 0 and rep["bad_index_rows"] == 0, rep
     assert np.all(np.diff(dist, axis=1) >= 0)
     return rep
 
