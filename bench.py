@@ -390,7 +390,7 @@ def bench_batched(args):
         del Rd
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b = K.Batch(probs, "fp16", tune=True)
+    b = K.Batch(probs, "fp16", s_extra=args.batch_extra, tune=True)
     b.run()
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
@@ -422,7 +422,7 @@ def bench_batched(args):
         "data": "synthetic",
         "config": {"workload": f"batch{len(specs)}", "instances": len(specs), "pairs": pairs,
                    "m": [1000, 200000], "n": [16, 4096], "d": [16, 32, 64, 128], "k": [1, 8, 32, 100],
-                   "graph": True, "tuned": True, "data": "uniform [0,1)"},
+                   "graph": True, "tuned": True, "data": "uniform [0,1)", "s_extra": args.batch_extra},
         "eager_ms_per_step": sec_e * 1e3,
         "roofline": roof,
         "kernels": {"graph": kern, "eager": kern_e},
@@ -810,6 +810,9 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=2048,
                     help="precision mode: seeded queries checked against the FP64 oracle (recall@k sample)")
     ap.add_argument("--instances", type=int, default=512, help="batched mode: number of instances")
+    ap.add_argument("--batch-extra", type=int, default=28,
+                    help="batched mode: extra candidates re-ranked per query (k + extra <= 128 keeps every instance, "
+                         "k up to 100, in the one launch of the 32x32-tile kernel)")
     ap.add_argument("--requests", type=int, default=10000, help="serve mode: requests per trace")
     ap.add_argument("--sizes", default="uniform", choices=["uniform", "loguniform"],
                     help="serve mode: request size distribution")

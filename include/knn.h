@@ -30,6 +30,12 @@
  *     squared differences), not its square.
  *   - Requirements: n >= 0 (n == 0 is a no-op), m >= 1, d >= 1,
  *     1 <= k <= m (k == m returns every reference).
+ *   - Limit of this implementation: the fused kernels keep at most 448
+ *     candidates per query, so k' = min(m, k + s) <= 448, where s is the
+ *     number of extra candidates re-ranked (8 for knn_search and the float32
+ *     forms, 32 by default for the 16-bit forms, s_extra where a call takes
+ *     it): knn_search accepts k <= 440 (or any k <= m when m <= 448).  A
+ *     larger k' returns KNN_ERR_UNSUPPORTED before anything is enqueued.
  *   - Inputs containing NaN or infinity are outside the contract.
  *   - Handles are not thread-safe; distinct handles may be used from
  *     distinct threads.
@@ -102,12 +108,19 @@ int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, 
  *   dist [n][k], idx [n][k]: device outputs, as for knn_search.
  * Q and R are translated by the mean of R's first 256 rows and mapped by
  * L^T in float32 (one fused multiply-add per term, ascending t); the
- * Euclidean search of knn_search then runs on the mapped points.  Distances
- * are exact float32 difference-form distances of the mapped points, so they
- * differ from the FP64 d_M by the rounding of the mapping (a relative error
- * of about d 2^-24 |L^T (x - c)| / d_M).
- * Scratch of (n + m) d 4 bytes is allocated and released in stream order.
- * Errors: as knn_search; KNN_ERR_INVALID also for a NULL L.
+ * Euclidean search of knn_search on the mapped points keeps k' = k + 8
+ * candidates per query.  Their distances are then recomputed from the
+ * caller's rows: the difference q - r in float32, then L^T (q - r) and its
+ * squared norm accumulated in double precision in a fixed order, the square
+ * root rounded to float32; the k smallest by (distance, index) are returned.
+ * The returned distances are thus within a few float32 roundings of the
+ * FP64 d_M, however close q and r are relative to their distance from the
+ * set's centre.
+ * Scratch of (n + m) d 4 + 2 n k' 4 bytes is allocated and released in
+ * stream order.
+ * Errors: as knn_search; KNN_ERR_INVALID also for a NULL L;
+ * KNN_ERR_UNSUPPORTED when k' exceeds the search's limit or d the re-rank's
+ * (4 (d + 2 k') 4 bytes of LDS per workgroup).
  */
 int knn_search_mahalanobis(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, const float* L, int32_t k,
                            float* dist, int32_t* idx, void* stream);
@@ -337,7 +350,8 @@ int knn_server_destroy(knn_server_t srv);
  *     folds them into per-kernel totals and returns the summed duration (ms)
  *     and launch count of kernel family `name`: "centre", "prep_refs",
  *     "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
- *     "fused_l1_f32", "fused_linf_f32", "finalize".  Unknown names read 0.
+ *     "fused_l1_f32", "fused_linf_f32", "merge" (slice lists merged in
+ *     groups before the finalize), "finalize".  Unknown names read 0.
  *   knn_timing_reset(): waits for and discards everything recorded.
  * Errors: KNN_ERR_INVALID (NULL name), KNN_ERR_DEVICE.
  */

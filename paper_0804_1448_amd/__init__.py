@@ -22,7 +22,7 @@ __all__ = ["search", "search_mahalanobis", "classify", "entropy", "Refs", "Batch
            "timing"]
 
 KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
-           "fused_l1_f32", "fused_linf_f32", "finalize", "batch_graph")
+           "fused_l1_f32", "fused_linf_f32", "merge", "finalize", "batch_graph")
 
 
 class timing:

@@ -207,7 +207,31 @@ struct Plan {
   bool wide = false;  // the 32x32-tile Euclidean kernel with register lists
   bool lane = false;  // the one-query-per-lane Manhattan / infinity-norm kernel
   int nq = 128;       // queries per workgroup
+  int G = 1;          // slice lists merged per group before the finalize (1: none)
+  int P2 = 1;         // lists per query the finalize merges: ceil(P / G)
 };
+
+// Slices of a search: at most kMaxSlices, and at least max(kStepRefs, 4 k')
+// references each.  With k' <= 64, more than kFinalMaxKeys / k' lists per
+// query are first merged in groups (merge_lists_kernel); larger k' keeps the
+// finalize's limit.
+int64_t cap_slices(int64_t P, int kc, int64_t m) {
+  const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
+  const int64_t cap = kc <= 64 ? kMaxSlices : std::min<int64_t>(64, kFinalMaxKeys / kc);
+  return std::max<int64_t>(1, std::min<int64_t>({P, cap, pmax_len}));
+}
+
+// the merge groups of a plan with P slices
+void plan_merge(Plan& p) {
+  const int64_t p2max = std::min<int64_t>(64, kFinalMaxKeys / p.kc);
+  if (p.P <= p2max) {
+    p.G = 1;
+    p.P2 = p.P;
+    return;
+  }
+  p.G = (int)ceil_div(p.P, p2max);
+  p.P2 = (int)ceil_div(p.P, p.G);
+}
 
 bool is_half_kind(int kind) { return kind == TILE_L2_BF16 || kind == TILE_L2_F16; }
 
@@ -253,7 +277,8 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Pl
   // Euclidean with k' <= 64 and d <= 128: the 32x32-tile kernel with
   // register lists (KNN_FUSED_WIDE=0 selects the general kernel instead)
   const char* ewide = getenv("KNN_FUSED_WIDE");
-  if (kind <= TILE_L2_F16 && kc <= kWideMaxKc && p.dp <= kWideMaxDp && !(ewide && atoi(ewide) == 0)) {
+  const int wide_kc = kind == TILE_L2_F32 ? kWideMaxKc1 : kWideMaxKc;
+  if (kind <= TILE_L2_F16 && kc <= wide_kc && p.dp <= kWideMaxDp && !(ewide && atoi(ewide) == 0)) {
     p.wide = true;
     p.waves = 8;
     p.cb = 32;
@@ -261,14 +286,12 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Pl
     p.nchunk = 1;
     p.nq = kWideQueries;
     const int64_t nqb = ceil_div(n, (int64_t)p.nq);
-    int64_t P = ceil_div((int64_t)device_cu_count(), nqb);
-    const int64_t pmax_keys = kFinalMaxKeys / kc;
-    const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
-    P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
+    int64_t P = cap_slices(ceil_div((int64_t)device_cu_count(), nqb), kc, m);
     const int ep = env_int("KNN_FUSED_P");
-    if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
+    if (ep > 0) P = std::min<int64_t>({(int64_t)ep, cap_slices(ep, kc, m), ceil_div(m, kStepRefs)});
     p.slice_len = round_up(ceil_div(m, P), kStepRefs);
     p.P = (int)ceil_div(m, p.slice_len);
+    plan_merge(p);
     // Float32 steps are long, so the 32x32 kernel pays off only where its
     // per-query merges are spread over a long scan; shorter slices take the
     // float32 lane kernel (or the general kernel), and one-shot searches,
@@ -322,14 +345,12 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Pl
       // two waves per SIMD at most (register budget), fewer where LDS binds
       const int wg_per_cu = best / waves;
       const int64_t nqb = ceil_div(n, (int64_t)p.nq);
-      int64_t P = ceil_div((int64_t)device_cu_count() * wg_per_cu, nqb);
-      const int64_t pmax_keys = kFinalMaxKeys / kc;
-      const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
-      P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
+      int64_t P = cap_slices(ceil_div((int64_t)device_cu_count() * wg_per_cu, nqb), kc, m);
       const int ep = env_int("KNN_FUSED_P");
-      if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, m});
+      if (ep > 0) P = std::min<int64_t>({(int64_t)ep, cap_slices(ep, kc, m), m});
       p.slice_len = round_up(ceil_div(m, P), 32);
       p.P = (int)ceil_div(m, p.slice_len);
+      plan_merge(p);
       *out = p;
       return KNN_OK;
     }
@@ -364,14 +385,12 @@ int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Pl
   const int wg_per_cu = std::max<int>(1, (int)(kLdsBytes / lds));
   const int64_t nqb = ceil_div(n, (int64_t)p.nq);
   const int64_t target = (int64_t)device_cu_count() * wg_per_cu;
-  int64_t P = ceil_div(target, nqb);
-  const int64_t pmax_keys = kFinalMaxKeys / kc;
-  const int64_t pmax_len = std::max<int64_t>(1, m / std::max<int64_t>(kStepRefs, 4 * (int64_t)kc));
-  P = std::max<int64_t>(1, std::min<int64_t>({P, (int64_t)64, pmax_keys, pmax_len}));
+  int64_t P = cap_slices(ceil_div(target, nqb), kc, m);
   const int ep = env_int("KNN_FUSED_P");
-  if (ep > 0) P = std::min<int64_t>({(int64_t)ep, pmax_keys, ceil_div(m, kStepRefs)});
+  if (ep > 0) P = std::min<int64_t>({(int64_t)ep, cap_slices(ep, kc, m), ceil_div(m, kStepRefs)});
   p.slice_len = round_up(ceil_div(m, P), kStepRefs);
   p.P = (int)ceil_div(m, p.slice_len);
+  plan_merge(p);
   *out = p;
   return KNN_OK;
 }
@@ -416,7 +435,9 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   const size_t hbytes = prep_refs && l2 ? (size_t)round_up(a.m * 4, 256) : 0;
   const size_t qbytes = prep_q ? (size_t)round_up(a.n * plan.dp * plan.es, 256) : 0;
   const size_t kbytes = (size_t)round_up(a.n * plan.P * (int64_t)plan.kc * 8, 256);
-  const size_t total = cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes;
+  const size_t k2bytes = plan.G > 1 ? (size_t)round_up(a.n * plan.P2 * (int64_t)plan.kc * 8, 256) : 0;
+  const size_t tbytes = a.nsubs > 0 ? sub_tables_bytes(a.nsubs, a.n) : 0;
+  const size_t total = cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes + k2bytes + tbytes;
   if (need) *need = total;
   if (!ws_in) return KNN_OK;
   if (ws_size < total) return fail(KNN_ERR_INVALID, "workspace of %zu bytes is smaller than the %zu needed", ws_size, total);
@@ -426,6 +447,8 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   float* wrhalf = (float*)(wrows + rbytes);
   unsigned char* wq = wrows + rbytes + hbytes;
   uint64_t* part = (uint64_t*)(wq + qbytes);
+  uint64_t* part2 = (uint64_t*)((unsigned char*)part + kbytes);
+  unsigned char* tables = (unsigned char*)part2 + k2bytes;
 
   const void* rows = a.rows;
   int ldr = a.ldr;
@@ -493,9 +516,14 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
     HIP_TRY(launch_fused(a.kind, fp, a.stream), "fused distance/selection launch");
   }
 
+  if (plan.G > 1) {
+    TimedLaunch tl("merge", a.stream);
+    HIP_TRY(launch_merge_lists(part, part2, a.n, plan.P, plan.kc, plan.G, plan.P2, a.stream), "slice-list merge launch");
+  }
+
   FinalParams fin{};
   FinalInst& f1 = fin.one;
-  f1.part = part;
+  f1.part = plan.G > 1 ? part2 : part;
   f1.Q = a.Q;
   f1.ldq = a.d;
   if (one_shot) {
@@ -512,7 +540,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   f1.n = a.n;
   f1.m = a.m;
   f1.d = a.d;
-  f1.P = plan.P;
+  f1.P = plan.P2;
   f1.kc = plan.kc;
   f1.kprime = a.kprime;
   f1.k = a.k;
@@ -520,14 +548,45 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   fin.insts = nullptr;
   fin.items = nullptr;
   fin.nitems = 0;
-  fin.keys_max = plan.P * plan.kc;
-  fin.p_max = plan.P;
+  fin.keys_max = plan.P2 * plan.kc;
+  fin.p_max = plan.P2;
   fin.kprime_max = a.kprime;
+  if (a.nsubs > 0) {
+    // one finalize instance per request, each with its own k and k': the
+    // first k'_i keys of a row's merged top-k' list are that row's top k'_i
+    FinalInst* ti = (FinalInst*)a.tables_host;
+    FinalItem* tt = (FinalItem*)((unsigned char*)a.tables_host + round_up(a.nsubs * (int64_t)sizeof(FinalInst), 16));
+    int nitems = 0;
+    for (int i = 0; i < a.nsubs; ++i) {
+      const SubSearch& sb = a.subs[i];
+      if (sb.row0 < 0 || sb.n < 1 || sb.row0 + sb.n > a.n || sb.kprime > a.kprime || sb.k > sb.kprime || sb.k < 1)
+        return fail(KNN_ERR_INVALID, "request %d of the search does not fit it", i);
+      FinalInst fi = f1;
+      fi.part = f1.part + sb.row0 * (int64_t)plan.P2 * plan.kc;
+      fi.Q = a.Q + sb.row0 * (int64_t)a.d;
+      fi.dist = sb.dist;
+      fi.idx = sb.idx;
+      fi.n = sb.n;
+      fi.kprime = sb.kprime;
+      fi.k = sb.k;
+      ti[i] = fi;
+      for (int64_t q = 0; q < sb.n; q += kFinalWaves) tt[nitems++] = FinalItem{i, (int)q};
+    }
+    HIP_TRY(hipMemcpyAsync(tables, a.tables_host, tbytes, hipMemcpyHostToDevice, a.stream), "finalize tables copy");
+    fin.insts = (const FinalInst*)tables;
+    fin.items = (const FinalItem*)(tables + ((unsigned char*)tt - (unsigned char*)ti));
+    fin.nitems = nitems;
+  }
   {
     TimedLaunch tl("finalize", a.stream);
     HIP_TRY(launch_finalize(fin, a.stream), "finalize launch");
   }
   return KNN_OK;
+}
+
+size_t sub_tables_bytes(int nsubs, int64_t n) {
+  const int64_t items = n / kFinalWaves + nsubs;  // >= sum over requests of ceil(n_i / kFinalWaves)
+  return (size_t)round_up(round_up(nsubs * (int64_t)sizeof(FinalInst), 16) + items * (int64_t)sizeof(FinalItem), 256);
 }
 
 // Run one search in the library's per-stream workspace.
@@ -707,21 +766,38 @@ int knn_search_mahalanobis(const float* Q, int64_t n, const float* R, int64_t m,
   if ((st = check_ptr(Q, "Q")) || (st = check_ptr(R, "R")) || (st = check_ptr(L, "L")) ||
       (st = check_ptr(dist, "dist")) || (st = check_ptr(idx, "idx")))
     return st;
+  // candidates: the k' = k + 8 nearest of the mapped points (Euclidean
+  // search); then their exact distances from the caller's rows
+  const int kc = (int)std::min<int64_t>(m, (int64_t)k + default_extra(KNN_FP32));
+  if ((size_t)4 * (d + 2 * kc) * 4 > (size_t)kLdsBytes)
+    return fail(KNN_ERR_UNSUPPORTED, "d = %d is too large for the Mahalanobis re-rank", d);
+  {
+    SearchArgs probe{};
+    if ((st = one_shot_args(Q, n, R, m, d, kc, KNN_L2, dist, idx, (hipStream_t)stream, &probe)) != KNN_OK) return st;
+    size_t need = 0;
+    if ((st = run_search_ws(probe, nullptr, 0, &need)) != KNN_OK) return st;  // k' beyond the kernels' limit
+  }
   hipStream_t s = (hipStream_t)stream;
   const size_t cbytes = round_up((int64_t)d * 4, 256), qbytes = round_up(n * d * 4, 256),
-               rbytes = round_up(m * d * 4, 256);
+               rbytes = round_up(m * d * 4, 256), kbytes = round_up(n * (int64_t)kc * 4, 256);
   void* scratch = nullptr;
-  if (hipMallocAsync(&scratch, cbytes + qbytes + rbytes, s) != hipSuccess) {
+  if (hipMallocAsync(&scratch, cbytes + qbytes + rbytes + 2 * kbytes, s) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(KNN_ERR_OOM, "cannot allocate %zu bytes of Mahalanobis scratch", cbytes + qbytes + rbytes);
+    return fail(KNN_ERR_OOM, "cannot allocate %zu bytes of Mahalanobis scratch", cbytes + qbytes + rbytes + 2 * kbytes);
   }
   float* c = (float*)scratch;
   float* Qt = (float*)((unsigned char*)scratch + cbytes);
   float* Rt = (float*)((unsigned char*)scratch + cbytes + qbytes);
+  float* cdist = (float*)((unsigned char*)scratch + cbytes + qbytes + rbytes);
+  int32_t* cidx = (int32_t*)((unsigned char*)cdist + kbytes);
   hipError_t e = launch_centre(R, m, d, d, c, s);
   if (e == hipSuccess) e = launch_transform_rows(Q, n, d, c, L, Qt, s);
   if (e == hipSuccess) e = launch_transform_rows(R, m, d, c, L, Rt, s);
-  st = e == hipSuccess ? knn_search(Qt, n, Rt, m, d, k, KNN_L2, dist, idx, stream) : hip_fail(e, "Mahalanobis transform");
+  st = e == hipSuccess ? knn_search(Qt, n, Rt, m, d, kc, KNN_L2, cdist, cidx, stream) : hip_fail(e, "Mahalanobis transform");
+  if (st == KNN_OK) {
+    e = launch_mahalanobis_rerank(Q, R, L, n, d, m, cidx, kc, dist, idx, k, s);
+    if (e != hipSuccess) st = hip_fail(e, "Mahalanobis re-rank");
+  }
   const hipError_t ef = hipFreeAsync(scratch, s);
   if (st == KNN_OK && ef != hipSuccess) st = hip_fail(ef, "Mahalanobis scratch release");
   return st;
@@ -920,56 +996,78 @@ struct BatchInst {
   int group = 0;
   int64_t slice_len = 0;
   size_t q_off = 0;     // prepared queries in the workspace
-  size_t part_off = 0;  // candidate lists in the workspace
+  size_t part_off = 0;  // candidate lists in the workspace (sized for the most slices a configuration gives)
 };
 
-// Instances sharing one fused launch: same tile kind, padded dimension and
-// k' class (k' <= 64 takes the register merge).
+// A launch configuration of a group: (waves, cb) of the general kernel, or
+// (8, kWideCb) for the 32x32-tile kernel with register lists; and the
+// reference slice length of the group's work items.
+constexpr int kWideCb = 0;
+
+struct GroupConfig {
+  int waves = 8;
+  int cb = kWideCb;
+  int64_t slice = 0;
+};
+
+// Instances sharing one fused launch.  Every 16-bit Euclidean instance with
+// k' <= 128 and a padded dimension <= 128 belongs to the one-launch group
+// (`one`), which the 32x32-tile kernel serves with one workgroup per item;
+// the others are grouped by tile kind, padded dimension and k' class.
 struct BatchGroup {
   int kind = 0;
   int dp = 0;
   int kclass = 0;
+  bool one = false;
   int ng = 1;
   int nchunk = 1;
-  int waves = 8;
-  int cb = 64;
   int kc_max = 0;
+  GroupConfig cfg;
+  int64_t base_slice = 0;  // the default slice length
   std::vector<int> insts;
-  size_t insts_off = 0;  // FusedInst table in the workspace
-  size_t items_off = 0;  // FusedItem list (sized for the smallest wave count tried)
+  size_t insts_off = 0;    // FusedInst table in the workspace
+  size_t items_off = 0;    // FusedItem list (sized for the configuration with the most items)
   int nitems = 0;
   bool tuned = false;
 };
 
-// A launch configuration is (waves, cb) of the general kernel, or
-// (8, kWideCb) for the 16-bit kernel with 32x32 tiles and register lists.
-constexpr int kWideCb = 0;
+// queries per workgroup of a configuration
+int config_nq(const GroupConfig& c) { return c.cb == kWideCb ? kWideQueries : c.waves * kQueriesPerWave; }
 
 bool group_wide_ok(const BatchGroup& g) {
-  return is_half_kind(g.kind) && g.kc_max <= kWideMaxKc && g.dp <= kWideMaxDp;
+  const int lim = g.kind == TILE_L2_F32 ? kWideMaxKc1 : kWideMaxKc;
+  return g.kind <= TILE_L2_F16 && g.kc_max <= lim && g.dp <= kWideMaxDp;
 }
 
-// queries per workgroup of a configuration
-int config_nq(int waves, int cb) { return cb == kWideCb ? kWideQueries : waves * kQueriesPerWave; }
+int64_t clamp_slice(int64_t s) { return std::max<int64_t>(16 * kStepRefs, round_up(std::max<int64_t>(1, s), kStepRefs)); }
 
-// candidate launch configurations of a group, best first
-std::vector<std::pair<int, int>> group_configs(const BatchGroup& g) {
-  std::vector<std::pair<int, int>> out;
-  if (group_wide_ok(g)) out.push_back({8, kWideCb});
+// candidate launch configurations of a group, the default first
+std::vector<GroupConfig> group_configs(const BatchGroup& g) {
+  std::vector<GroupConfig> out;
+  if (g.one) {
+    // tile shape fixed (256 queries x 64 references per step); the tuner
+    // picks the slice length, which sets the number and size of the items
+    for (int64_t s : {g.base_slice, g.base_slice / 2, g.base_slice * 2, g.base_slice / 4})
+      out.push_back({8, kWideCb, clamp_slice(s)});
+    return out;
+  }
+  if (group_wide_ok(g)) out.push_back({8, kWideCb, g.base_slice});
   const int group = group_dims(g.kind);
   for (int waves : {8, 4, 2}) {
     for (int cb : {64, 96, 128}) {
       if (g.kc_max <= 64 && cb != 64) continue;
       if (g.kc_max + cb > 64 * kMaxMergePerLane) continue;
       if (fused_lds_bytes(g.kind, waves, g.kc_max, cb, g.ng * group) > (size_t)kLdsBytes) continue;
-      out.push_back({waves, cb});
+      out.push_back({waves, cb, g.base_slice});
     }
   }
   return out;
 }
 
 // tuned configurations of this process (and of a text cache file when
-// KNN_TUNE_CACHE names one), keyed by "kind/dp/kclass/size bucket"
+// KNN_TUNE_CACHE names one), keyed by "kind/dp/kclass/size bucket": waves,
+// cb and the slice length as a fraction of the default (index into the
+// candidate list for the one-launch group)
 std::mutex g_tune_mutex;
 std::map<std::string, std::pair<int, int>> g_tune;
 bool g_tune_loaded = false;
@@ -981,7 +1079,10 @@ std::string tune_key(const BatchGroup& g, int64_t pairs) {
     ++bucket;
   }
   char buf[96];
-  snprintf(buf, sizeof buf, "v2/k%d/d%d/c%d/s%d", g.kind, g.dp, g.kclass, bucket);
+  if (g.one)
+    snprintf(buf, sizeof buf, "v3/one/k%d/s%d", g.kind, bucket);
+  else
+    snprintf(buf, sizeof buf, "v3/k%d/d%d/c%d/s%d", g.kind, g.dp, g.kclass, bucket);
   return buf;
 }
 
@@ -994,7 +1095,7 @@ void tune_load() {
   if (!f) return;
   char key[96];
   int w = 0, cb = 0;
-  // one entry per line: "key waves cb"
+  // one entry per line: "key a b" (general: waves cb; one-launch group: candidate index, -1)
   while (fscanf(f, "%95s %d %d", key, &w, &cb) == 3) g_tune[key] = {w, cb};
   fclose(f);
 }
@@ -1016,9 +1117,12 @@ struct knn_batch_s {
   int flags = 0;
   std::vector<BatchInst> inst;
   std::vector<BatchGroup> groups;
+  std::vector<FinalInst> finsts;  // host copy of the finalize table
   void* ws = nullptr;
   size_t ws_size = 0;
   size_t jobs_off = 0;
+  size_t counter_off = 0;  // item counter of the one-launch group
+  bool has_one = false;
   int64_t prep_rows = 0;
   size_t finsts_off = 0, fitems_off = 0;
   int nfitems = 0, keys_max = 0, p_max = 1, kprime_max = 0;
@@ -1032,36 +1136,48 @@ namespace knn::host {
 
 bool valid_batch(knn_batch_t b) { return b && b->magic == 0x6b6e6e42u; }
 
-// items of group g for a launch configuration, longest first
-std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, int waves, int cb) {
+int64_t pmax_of(const BatchInst& in) { return std::max<int64_t>(1, std::min<int64_t>(64, kFinalMaxKeys / in.kc)); }
+
+// slices of an instance at slice length `slice`: (P, slice_len)
+std::pair<int, int64_t> slicing(const BatchInst& in, int64_t slice) {
+  const int64_t m = in.prob.refs->m;
+  const int64_t P = std::min<int64_t>(pmax_of(in), ceil_div(m, slice));
+  const int64_t len = round_up(ceil_div(m, P), kStepRefs);
+  return {(int)ceil_div(m, len), len};
+}
+
+// items of group g, longest first: cost = query columns of the block x
+// references of the slice x (padded dimension + a fixed selection share)
+std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, const GroupConfig& c) {
   struct Cost {
     int64_t cost;
     FusedItem it;
   };
   std::vector<Cost> all;
-  const int nq = config_nq(waves, cb);
+  const int nq = config_nq(c);
   for (size_t j = 0; j < g.insts.size(); ++j) {
     const BatchInst& in = b.inst[g.insts[j]];
+    const auto sl = slicing(in, c.slice);
     const int64_t qb = ceil_div(in.prob.n, nq);
     for (int64_t q = 0; q < qb; ++q) {
       const int64_t rows = std::min<int64_t>(nq, in.prob.n - q * nq);
-      for (int sl = 0; sl < in.P; ++sl) {
-        const int64_t refs = std::min<int64_t>(in.slice_len, in.prob.refs->m - sl * in.slice_len);
+      for (int s = 0; s < sl.first; ++s) {
+        const int64_t refs = std::min<int64_t>(sl.second, in.prob.refs->m - s * sl.second);
         // a block costs its full width of queries whatever its fill
-        Cost c;
-        c.cost = (int64_t)nq * refs + rows;
-        c.it.inst = (int)j;
-        c.it.qblock = (int)q;
-        c.it.slice = sl;
-        c.it.pad = 0;
-        all.push_back(c);
+        Cost e;
+        e.cost = (int64_t)nq * refs * (in.dp + 64) + rows;
+        e.it.inst = (int)j;
+        e.it.qblock = (int)q;
+        e.it.slice = s;
+        e.it.pad = 0;
+        all.push_back(e);
       }
     }
   }
   std::stable_sort(all.begin(), all.end(), [](const Cost& x, const Cost& y) { return x.cost > y.cost; });
   std::vector<FusedItem> items;
   items.reserve(all.size());
-  for (auto& c : all) items.push_back(c.it);
+  for (auto& e : all) items.push_back(e.it);
   return items;
 }
 
@@ -1071,27 +1187,70 @@ int upload(void* dst, const void* src, size_t bytes) {
   return KNN_OK;
 }
 
-// Fill the group's fused-launch parameters for `waves`/`cb`.
-FusedParams group_params(knn_batch_s& b, const BatchGroup& g, int waves, int cb, int nitems) {
+// The group's fused-launch parameters for its current configuration.
+FusedParams group_params(knn_batch_s& b, const BatchGroup& g) {
   FusedParams fp{};
   unsigned char* w = (unsigned char*)b.ws;
   fp.insts = (const FusedInst*)(w + g.insts_off);
   fp.items = (const FusedItem*)(w + g.items_off);
-  fp.nitems = nitems;
-  fp.wide = cb == kWideCb ? 1 : 0;
+  fp.nitems = g.nitems;
+  fp.wide = g.cfg.cb == kWideCb ? 1 : 0;
   fp.ng = fp.wide ? g.dp / 16 : g.ng;
-  fp.cb = fp.wide ? 32 : cb;
-  fp.waves = waves;
+  fp.cb = fp.wide ? 32 : g.cfg.cb;
+  fp.waves = g.cfg.waves;
   fp.kc_max = g.kc_max;
+  fp.counter = g.one ? (int*)(w + b.counter_off) : nullptr;
   return fp;
 }
 
-int batch_set_group_config(knn_batch_s& b, BatchGroup& g, int waves, int cb) {
-  std::vector<FusedItem> items = group_items(b, g, waves, cb);
-  int st = upload((unsigned char*)b.ws + g.items_off, items.data(), items.size() * sizeof(FusedItem));
+// Apply configuration `c` to group g: slicing of its instances, its
+// instance table and items, and the finalize table.
+int batch_set_group_config(knn_batch_s& b, BatchGroup& g, const GroupConfig& c) {
+  unsigned char* w = (unsigned char*)b.ws;
+  std::vector<FusedInst> fis;
+  for (int j : g.insts) {
+    BatchInst& in = b.inst[j];
+    const auto sl = slicing(in, c.slice);
+    in.P = sl.first;
+    in.slice_len = sl.second;
+    const knn_refs_s* r = in.prob.refs;
+    FusedInst fi{};
+    fi.Q = w + in.q_off;
+    if (in.kind <= TILE_L2_F16) {
+      fi.R = r->rows;
+      fi.ldr = r->dp;
+      fi.rhalf = r->rhalf;
+    } else {
+      fi.R = r->master;
+      fi.ldr = r->dp32;
+      fi.rhalf = nullptr;
+    }
+    fi.part = (uint64_t*)(w + in.part_off);
+    fi.n = in.prob.n;
+    fi.m = r->m;
+    fi.slice_len = in.slice_len;
+    fi.ldq = in.dp;
+    fi.dp = in.dp;
+    fi.nchunk = g.nchunk;
+    fi.P = in.P;
+    fi.kc = in.kc;
+    fis.push_back(fi);
+    b.finsts[j].P = in.P;
+  }
+  int st = upload(w + g.insts_off, fis.data(), fis.size() * sizeof(FusedInst));
   if (st != KNN_OK) return st;
-  g.waves = waves;
-  g.cb = cb;
+  std::vector<FusedItem> items = group_items(b, g, c);
+  st = upload(w + g.items_off, items.data(), items.size() * sizeof(FusedItem));
+  if (st != KNN_OK) return st;
+  st = upload(w + b.finsts_off, b.finsts.data(), b.finsts.size() * sizeof(FinalInst));
+  if (st != KNN_OK) return st;
+  b.keys_max = 0;
+  b.p_max = 1;
+  for (const BatchInst& in : b.inst) {
+    b.keys_max = std::max(b.keys_max, in.P * in.kc);
+    b.p_max = std::max(b.p_max, in.P);
+  }
+  g.cfg = c;
   g.nitems = (int)items.size();
   return KNN_OK;
 }
@@ -1101,11 +1260,13 @@ int batch_enqueue(knn_batch_s& b, hipStream_t s) {
   unsigned char* w = (unsigned char*)b.ws;
   {
     TimedLaunch tl("prep_queries", s);
-    HIP_TRY(launch_prep_batched((const PrepJob*)(w + b.jobs_off), (int)b.inst.size(), b.prep_rows, s),
+    HIP_TRY(launch_prep_batched((const PrepJob*)(w + b.jobs_off), (int)b.inst.size(), b.prep_rows, s,
+                                b.has_one ? (int*)(w + b.counter_off) : nullptr),
             "batched query preparation launch");
   }
   for (BatchGroup& g : b.groups) {
-    FusedParams fp = group_params(b, g, g.waves, g.cb, g.nitems);
+    if (g.nitems == 0) continue;
+    FusedParams fp = group_params(b, g);
     TimedLaunch tl(fused_name(g.kind), s);
     HIP_TRY(launch_fused(g.kind, fp, s), "batched fused launch");
   }
@@ -1132,27 +1293,42 @@ int batch_tune(knn_batch_s& b, hipStream_t s) {
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
   int st = KNN_OK;
+  unsigned char* w = (unsigned char*)b.ws;
   for (BatchGroup& g : b.groups) {
-    if (g.tuned) continue;
+    if (g.tuned || g.insts.empty()) continue;
     int64_t pairs = 0;
     for (int j : g.insts) pairs += b.inst[j].prob.n * b.inst[j].prob.refs->m;
     const std::string key = tune_key(g, pairs);
+    const std::vector<GroupConfig> cands = group_configs(g);
     auto hit = g_tune.find(key);
     if (hit != g_tune.end()) {
-      st = batch_set_group_config(b, g, hit->second.first, hit->second.second);
+      GroupConfig c = cands[0];
+      if (g.one) {
+        if (hit->second.first >= 0 && hit->second.first < (int)cands.size()) c = cands[hit->second.first];
+      } else {
+        for (const GroupConfig& x : cands)
+          if (x.waves == hit->second.first && x.cb == hit->second.second) c = x;
+      }
+      st = batch_set_group_config(b, g, c);
       if (st != KNN_OK) break;
       g.tuned = true;
       continue;
     }
     float best = 1e30f;
-    std::pair<int, int> best_cfg{g.waves, g.cb};
-    for (auto cfg : group_configs(g)) {
-      st = batch_set_group_config(b, g, cfg.first, cfg.second);
+    int best_i = 0;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      st = batch_set_group_config(b, g, cands[ci]);
       if (st != KNN_OK) break;
-      FusedParams fp = group_params(b, g, g.waves, g.cb, g.nitems);
-      hipError_t e = launch_fused(g.kind, fp, s);  // warm-up
+      FusedParams fp = group_params(b, g);
+      auto one_launch = [&]() {
+        hipError_t e = hipSuccess;
+        if (g.one) e = hipMemsetAsync(w + b.counter_off, 0, sizeof(int), s);  // outside any graph
+        if (e == hipSuccess) e = launch_fused(g.kind, fp, s);
+        return e;
+      };
+      hipError_t e = one_launch();  // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_fused(g.kind, fp, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = one_launch();
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -1163,13 +1339,13 @@ int batch_tune(knn_batch_s& b, hipStream_t s) {
       }
       if (ms < best) {
         best = ms;
-        best_cfg = cfg;
+        best_i = (int)ci;
       }
     }
     if (st != KNN_OK) break;
-    st = batch_set_group_config(b, g, best_cfg.first, best_cfg.second);
+    st = batch_set_group_config(b, g, cands[best_i]);
     if (st != KNN_OK) break;
-    g_tune[key] = best_cfg;
+    g_tune[key] = g.one ? std::make_pair(best_i, -1) : std::make_pair(cands[best_i].waves, cands[best_i].cb);
     g.tuned = true;
   }
   (void)hipEventDestroy(e0);
@@ -1202,8 +1378,10 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
   b->precision = precision;
   b->flags = flags;
   const int extra = s_extra < 0 ? default_extra(precision) : s_extra;
-  // ---- check and plan every instance
+  const bool one_ok = env_int("KNN_BATCH_ONE") >= 0;  // KNN_BATCH_ONE=-1: per-group launches (tests)
+  // ---- check and group every instance
   std::map<std::tuple<int, int, int>, int> group_of;
+  int one_group = -1;
   for (int i = 0; i < count; ++i) {
     const knn_problem_t& pr = probs[i];
     if (!valid_refs(pr.refs)) return fail(KNN_ERR_INVALID, "instance %d: not a live reference-set handle", i);
@@ -1223,64 +1401,69 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     in.es = is_half_kind(in.kind) ? 2 : 4;
     in.kprime = (int)std::min<int64_t>(r->m, (int64_t)pr.k + extra);
     in.kc = in.kprime;
-    const int kclass = in.kc <= 64 ? 0 : 1;
-    auto key = std::make_tuple(in.kind, in.dp, kclass);
-    auto it = group_of.find(key);
-    if (it == group_of.end()) {
-      BatchGroup g;
-      g.kind = in.kind;
-      g.dp = in.dp;
-      g.kclass = kclass;
-      it = group_of.emplace(key, (int)b->groups.size()).first;
-      b->groups.push_back(g);
+    const bool one = one_ok && is_half_kind(in.kind) && in.kc <= kWideMaxKc && in.dp <= kWideMaxDp;
+    if (one) {
+      if (one_group < 0) {
+        BatchGroup g;
+        g.kind = in.kind;
+        g.one = true;
+        one_group = (int)b->groups.size();
+        b->groups.push_back(g);
+      }
+      in.group = one_group;
+    } else {
+      const int kclass = in.kc <= 64 ? 0 : 1;
+      auto key = std::make_tuple(in.kind, in.dp, kclass);
+      auto it = group_of.find(key);
+      if (it == group_of.end()) {
+        BatchGroup g;
+        g.kind = in.kind;
+        g.dp = in.dp;
+        g.kclass = kclass;
+        it = group_of.emplace(key, (int)b->groups.size()).first;
+        b->groups.push_back(g);
+      }
+      in.group = it->second;
     }
-    in.group = it->second;
     BatchGroup& g = b->groups[in.group];
     g.kc_max = std::max(g.kc_max, in.kc);
+    g.dp = std::max(g.dp, in.dp);
     if (pr.n > 0) g.insts.push_back((int)b->inst.size());
     b->inst.push_back(in);
   }
-  // ---- launch configuration and slicing of each group
+  b->has_one = one_group >= 0;
+  // ---- default configuration and slice length of each group
   const int cus = device_cu_count();
   for (BatchGroup& g : b->groups) {
     const int group = group_dims(g.kind);
     const int total = g.dp / group;
     const int gmax = g.kind == TILE_L2_F32 ? kMaxGroupsF32 : is_half_kind(g.kind) ? kMaxGroups16 : kMaxGroupsValu;
-    // the widest chunk at which the general kernel fits; the default
-    // configuration is the first candidate (the 32x32-tile kernel where it
-    // applies)
-    bool general = false;
-    for (int ng = std::min(total, gmax); ng >= 1 && !general; --ng) {
-      g.ng = ng;
-      for (auto cfg : group_configs(g)) general = general || cfg.second != kWideCb;
+    if (!g.one) {
+      // the widest chunk at which the general kernel fits
+      bool general = false;
+      for (int ng = std::min(total, gmax); ng >= 1 && !general; --ng) {
+        g.ng = ng;
+        for (const GroupConfig& c : group_configs(g)) general = general || c.cb != kWideCb;
+      }
+      if (group_configs(g).empty())
+        return fail(KNN_ERR_UNSUPPORTED, "k' = %d candidates per query do not fit the fused kernel's LDS budget",
+                    g.kc_max);
+      g.nchunk = (int)ceil_div(total, g.ng);
     }
-    const auto cfgs = group_configs(g);
-    if (cfgs.empty())
-      return fail(KNN_ERR_UNSUPPORTED, "k' = %d candidates per query do not fit the fused kernel's LDS budget",
-                  g.kc_max);
-    g.waves = cfgs[0].first;
-    g.cb = cfgs[0].second;
-    g.nchunk = (int)ceil_div(total, g.ng);
     // slice length: about four items per workgroup slot of the whole device
-    // (for the default configuration: the first of group_configs)
-    const int nq = config_nq(g.waves, g.cb);
-    const size_t lds =
-        g.cb == kWideCb ? kWideLdsBytes : fused_lds_bytes(g.kind, g.waves, g.kc_max, g.cb, g.ng * group);
+    // for the default configuration
+    const GroupConfig c0 = g.one ? GroupConfig{8, kWideCb, 0} : group_configs(g)[0];
+    const int nq = config_nq(c0);
+    const size_t lds = c0.cb == kWideCb ? kWideLdsBytes
+                                         : fused_lds_bytes(g.kind, c0.waves, g.kc_max, c0.cb, g.ng * group);
     const int64_t slots = (int64_t)cus * std::max<int>(1, (int)(kLdsBytes / lds));
     int64_t blockrefs = 0;
     for (int j : g.insts) blockrefs += ceil_div(b->inst[j].prob.n, nq) * b->inst[j].prob.refs->m;
-    int64_t slice = round_up(std::max<int64_t>(1, blockrefs / std::max<int64_t>(1, 4 * slots)), kStepRefs);
-    slice = std::max<int64_t>(slice, 16 * kStepRefs);
-    for (int j : g.insts) {
-      BatchInst& in = b->inst[j];
-      const int64_t m = in.prob.refs->m;
-      const int64_t pmax = std::max<int64_t>(1, std::min<int64_t>(64, kFinalMaxKeys / in.kc));
-      const int64_t P = std::min<int64_t>(pmax, ceil_div(m, slice));
-      in.slice_len = round_up(ceil_div(m, P), kStepRefs);
-      in.P = (int)ceil_div(m, in.slice_len);
-    }
+    g.base_slice = clamp_slice(blockrefs / std::max<int64_t>(1, 4 * slots));
+    g.cfg = c0;
+    g.cfg.slice = g.base_slice;
   }
-  // ---- workspace layout
+  // ---- workspace layout (part lists sized for the most slices any candidate gives)
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -1288,17 +1471,20 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     return at;
   };
   for (BatchInst& in : b->inst) {
+    int pmost = 1;
+    for (const GroupConfig& c : group_configs(b->groups[in.group])) pmost = std::max(pmost, slicing(in, c.slice).first);
     in.q_off = take((size_t)in.prob.n * in.dp * in.es);
-    in.part_off = take((size_t)in.prob.n * in.P * in.kc * 8);
+    in.part_off = take((size_t)in.prob.n * pmost * in.kc * 8);
   }
   for (BatchGroup& g : b->groups) {
     g.insts_off = take(g.insts.size() * sizeof(FusedInst));
     size_t most = 0;
-    for (auto cfg : group_configs(g)) most = std::max(most, group_items(*b, g, cfg.first, cfg.second).size());
+    for (const GroupConfig& c : group_configs(g)) most = std::max(most, group_items(*b, g, c).size());
     g.items_off = take(most * sizeof(FusedItem));
   }
   b->jobs_off = take(b->inst.size() * sizeof(PrepJob));
   b->finsts_off = take(b->inst.size() * sizeof(FinalInst));
+  b->counter_off = take(sizeof(int));
   int64_t nf = 0;
   for (BatchInst& in : b->inst) nf += ceil_div(in.prob.n, kFinalWaves);
   b->fitems_off = take((size_t)nf * sizeof(FinalItem));
@@ -1306,9 +1492,8 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
   if (int st0 = dev_alloc(&b->ws, b->ws_size, "batch workspace")) return st0;
   std::unique_ptr<knn_batch_s, void (*)(knn_batch_s*)> guard(b.get(), [](knn_batch_s* p) { free_batch(p); });
   unsigned char* w = (unsigned char*)b->ws;
-  // ---- descriptors: query preparation, fused instances and items, finalize
+  // ---- descriptors: query preparation, finalize, then each group's configuration
   std::vector<PrepJob> jobs;
-  std::vector<FinalInst> finsts;
   std::vector<FinalItem> fitems;
   int64_t row0 = 0;
   for (size_t i = 0; i < b->inst.size(); ++i) {
@@ -1346,53 +1531,24 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     fi.n = in.prob.n;
     fi.m = r->m;
     fi.d = r->d;
-    fi.P = in.P;
+    fi.P = 1;
     fi.kc = in.kc;
     fi.kprime = in.kprime;
     fi.k = in.prob.k;
     fi.metric = in.prob.metric;
-    finsts.push_back(fi);
+    b->finsts.push_back(fi);
     for (int64_t q = 0; q < in.prob.n; q += kFinalWaves) fitems.push_back({(int)i, (int)q});
-    b->keys_max = std::max(b->keys_max, in.P * in.kc);
-    b->p_max = std::max(b->p_max, in.P);
     b->kprime_max = std::max(b->kprime_max, in.kprime);
   }
   b->prep_rows = row0;
   b->nfitems = (int)fitems.size();
   int st = upload(w + b->jobs_off, jobs.data(), jobs.size() * sizeof(PrepJob));
-  if (st == KNN_OK) st = upload(w + b->finsts_off, finsts.data(), finsts.size() * sizeof(FinalInst));
   if (st == KNN_OK) st = upload(w + b->fitems_off, fitems.data(), fitems.size() * sizeof(FinalItem));
   for (BatchGroup& g : b->groups) {
     if (st != KNN_OK) break;
-    std::vector<FusedInst> fis;
-    for (int j : g.insts) {
-      const BatchInst& in = b->inst[j];
-      const knn_refs_s* r = in.prob.refs;
-      FusedInst fi{};
-      fi.Q = w + in.q_off;
-      if (in.kind <= TILE_L2_F16) {
-        fi.R = r->rows;
-        fi.ldr = r->dp;
-        fi.rhalf = r->rhalf;
-      } else {
-        fi.R = r->master;
-        fi.ldr = r->dp32;
-        fi.rhalf = nullptr;
-      }
-      fi.part = (uint64_t*)(w + in.part_off);
-      fi.n = in.prob.n;
-      fi.m = r->m;
-      fi.slice_len = in.slice_len;
-      fi.ldq = in.dp;
-      fi.dp = in.dp;
-      fi.nchunk = g.nchunk;
-      fi.P = in.P;
-      fi.kc = in.kc;
-      fis.push_back(fi);
-    }
-    st = upload(w + g.insts_off, fis.data(), fis.size() * sizeof(FusedInst));
-    if (st == KNN_OK) st = batch_set_group_config(*b, g, g.waves, g.cb);
+    st = batch_set_group_config(*b, g, g.cfg);
   }
+  if (st == KNN_OK) st = upload(w + b->finsts_off, b->finsts.data(), b->finsts.size() * sizeof(FinalInst));
   if (st != KNN_OK) return st;
   guard.release();
   *out = b.release();

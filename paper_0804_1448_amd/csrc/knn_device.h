@@ -249,6 +249,17 @@ __device__ __forceinline__ uint64_t bitonic_clean64(uint64_t v, int lane) {
   return v;
 }
 
+// sort a bitonic sequence of one key per lane descending
+__device__ __forceinline__ uint64_t bitonic_clean64_desc(uint64_t v, int lane) {
+  v = bitonic_step<32>(v, lane, false);
+  v = bitonic_step<16>(v, lane, false);
+  v = bitonic_step<8>(v, lane, false);
+  v = bitonic_step<4>(v, lane, false);
+  v = bitonic_step<2>(v, lane, false);
+  v = bitonic_step<1>(v, lane, false);
+  return v;
+}
+
 // Merge of a list of len <= kc <= 64 keys with a buffer of at most 64 keys
 // held one per lane: lane j loads buffer key j (segment j / 16, entry
 // j % 16).  The buffer is sorted descending across the wave; with the list

@@ -42,6 +42,17 @@ struct knn_refs_s {
 
 namespace knn::host {
 
+// Rows [row0, row0 + n) of a search that form one request with its own k,
+// k' (<= the search's k') and outputs dist [n][k], idx [n][k].
+struct SubSearch {
+  int64_t row0;
+  int64_t n;
+  int k;
+  int kprime;
+  float* dist;
+  int32_t* idx;
+};
+
 // One search, as the pipeline sees it.
 struct SearchArgs {
   const float* Q;        // caller's float32 queries [n][d]
@@ -63,7 +74,18 @@ struct SearchArgs {
   float* dist;
   int32_t* idx;
   hipStream_t stream;
+  // optional: the rows form `nsubs` requests, each finalized with its own k
+  // and k' into its own outputs (dist / idx above unused); their finalize
+  // tables are written to `tables_host` (pinned host memory of
+  // sub_tables_bytes(nsubs, n) bytes, valid until the search has run) and
+  // copied to the workspace on the stream
+  const SubSearch* subs = nullptr;
+  int nsubs = 0;
+  void* tables_host = nullptr;
 };
+
+// bytes of the finalize tables of a search of n rows split into nsubs requests
+size_t sub_tables_bytes(int nsubs, int64_t n);
 
 int fail(int status, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);

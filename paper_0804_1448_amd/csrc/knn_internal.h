@@ -80,6 +80,7 @@ struct FusedParams {
   int wide;             // 1: the 32x32-tile Euclidean kernel with register lists (ng = dp / 16)
   int lane;             // 1: a per-lane-selection kernel (ng = dp / 16; cb = queue keys per lane)
   int tiled;            // float32 Euclidean lane kernel: R in the 32-row tile layout (launch_prep_rows_tiled)
+  int* counter;         // one-launch batched form: next item to take (zeroed before the launch)
 };
 
 // One instance of the merge + exact re-rank + finalize kernel.
@@ -135,6 +136,7 @@ struct PrepJob {
 
 constexpr int kFinalWaves = 4;          // queries per finalize workgroup
 constexpr int kFinalMaxKeys = 2048;     // P * kc limit of one finalize wave
+constexpr int kMaxSlices = 256;         // slices of one search (above kFinalMaxKeys / kc: merged first, kc <= 64)
 constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
 
 // Launchers (knn_kernels.hip).  All enqueue on `stream` and return the HIP
@@ -159,7 +161,8 @@ KNN_FUSED_UNIT(l1_s) KNN_FUSED_UNIT(l1_l) KNN_FUSED_UNIT(linf_s) KNN_FUSED_UNIT(
 // Euclidean kernel with 32x32 tiles and register-resident lists (k' <= 64,
 // dp <= 128; float32 or 16-bit tiles): 8 waves of 32 queries per workgroup
 constexpr int kWideQueries = 256;
-constexpr int kWideMaxKc = 64;
+constexpr int kWideMaxKc1 = 64;   // one list key per lane
+constexpr int kWideMaxKc = 128;   // two keys per lane (16-bit tiles only)
 constexpr int kWideMaxDp = 128;
 constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice worth the 32x32 kernel
 // the same when the references can be read in the 32-row tile layout by the
@@ -178,18 +181,30 @@ hipError_t launch_lane(int kind, const FusedParams& p, hipStream_t stream);
 hipError_t launch_lane_l2(const FusedParams& p, hipStream_t stream);
 size_t lane_lds(int waves, int kc, int queue);
 hipError_t launch_finalize(const FinalParams& p, hipStream_t stream);
+// merge groups of G consecutive sorted slice lists per query (kc <= 64):
+// part [n][P][kc] -> out [n][P2][kc], P2 = ceil(P / G)
+hipError_t launch_merge_lists(const uint64_t* part, uint64_t* out, int64_t n, int P, int kc, int G, int P2,
+                              hipStream_t stream);
 // k-NN classification: out[q] = majority of labels[idx[q][0..k-1]] (ties to
 // the nearest of the tied classes)
 hipError_t launch_vote(const int32_t* idx, int64_t n, int k, const int32_t* labels, int32_t* out, hipStream_t stream);
 // Mahalanobis: Y = (X - c) L for rows of X [rows][d], c [d], L [d][d] (row-major)
 hipError_t launch_transform_rows(const float* X, int64_t rows, int d, const float* c, const float* L, float* Y,
                                  hipStream_t stream);
+// Mahalanobis: exact distances ||L^T (q - r)|| of kc candidates per query
+// (cidx [n][kc]) from the caller's rows, the k best written to dist / idx [n][k]
+hipError_t launch_mahalanobis_rerank(const float* Q, const float* R, const float* L, int64_t n, int d, int64_t m,
+                                     const int32_t* cidx, int kc, float* dist, int32_t* idx, int k,
+                                     hipStream_t stream);
 // k-NN entropy: per-point log rho_k from the k + 1 nearest (dist/idx
 // [n][k + 1]) into terms[n], then out = scale * sum(terms) + offset
 hipError_t launch_entropy(const float* dist, const int32_t* idx, int64_t n, int k, double* terms, double scale,
                           double offset, double* out, hipStream_t stream);
 
-hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream);
+// zero (may be NULL): an int set to 0 by the launch (the item counter of the
+// batched launch that follows on the stream)
+hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream,
+                               int* zero = nullptr);
 size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max);
 
 }  // namespace knn

@@ -431,6 +431,41 @@ size_t finalize_lds_bytes(int keys_max, int p_max, int kprime_max) {
   return finalize_wave_bytes(keys_max, p_max, kprime_max) * kFinalWaves;
 }
 
+// ------------------------------------------- merge of slice lists (kc <= 64)
+// Groups of G consecutive sorted lists of each query are merged into one:
+// part [n][P][kc] -> out [n][P2][kc], P2 = ceil(P / G).  One wave per
+// (query, group): the running list sits one key per lane, ascending; the
+// next list is loaded in reverse, so that the lane-wise minimum of the two
+// is a bitonic sequence holding the 64 smallest keys of both, which six
+// exchange stages sort.  Empty slots (all ones) sort last.
+__global__ __launch_bounds__(256) void merge_lists_kernel(const uint64_t* __restrict__ part, uint64_t* __restrict__ out,
+                                                          int64_t n, int P, int kc, int G, int P2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wv >= n * P2) return;
+  const int64_t q = wv / P2;
+  const int g = (int)(wv - q * P2);
+  const uint64_t* src = part + q * (int64_t)P * kc;
+  const int l0 = g * G, l1 = min(P, l0 + G);
+  uint64_t acc = lane < kc ? src[(int64_t)l0 * kc + lane] : kEmptyKey;
+  for (int l = l0 + 1; l < l1; ++l) {
+    const int e = 63 - lane;
+    const uint64_t x = e < kc ? src[(int64_t)l * kc + e] : kEmptyKey;
+    acc = bitonic_clean64(acc < x ? acc : x, lane);
+  }
+  if (lane < kc) out[(q * P2 + g) * (int64_t)kc + lane] = acc;
+}
+
+hipError_t launch_merge_lists(const uint64_t* part, uint64_t* out, int64_t n, int P, int kc, int G, int P2,
+                              hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (kc < 1 || kc > 64 || G < 1 || P2 != (P + G - 1) / G) return hipErrorInvalidValue;
+  const int64_t waves = n * P2;
+  hipLaunchKernelGGL(merge_lists_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, stream, part, out, n, P, kc,
+                     G, P2);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------ Mahalanobis transform
 // Y[i][j] = sum_t (X[i][t] - c[t]) L[t][j]: rows mapped by L^T after a common
 // translation by c (which cancels in every difference), one thread per output
@@ -453,6 +488,79 @@ hipError_t launch_transform_rows(const float* X, int64_t rows, int d, const floa
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(transform_rows_kernel, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, stream, X, rows,
                      d, c, L, Y);
+  return hipGetLastError();
+}
+
+// Exact re-rank of Mahalanobis candidates: for each query's kc candidates
+// (found by the Euclidean search of the mapped points), the distance
+// ||L^T (q - r)|| from the caller's rows: the difference q - r in float32,
+// then y = L^T (q - r) and sum y^2 accumulated in double precision in a
+// fixed order, rounded to float32; the k best by (distance, index) are
+// written.  One wave per query.
+__global__ __launch_bounds__(256) void mahalanobis_rerank_kernel(const float* __restrict__ Q,
+                                                                 const float* __restrict__ R,
+                                                                 const float* __restrict__ L, int64_t n, int d,
+                                                                 int64_t m, const int32_t* __restrict__ cidx, int kc,
+                                                                 float* __restrict__ dist, int32_t* __restrict__ idx,
+                                                                 int k) {
+  extern __shared__ __align__(16) unsigned char smem_mr[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  float* diff = (float*)smem_mr + (size_t)wave * (d + 2 * kc);
+  float* cd = diff + d;
+  int32_t* ci = (int32_t*)(cd + kc);
+  if (q >= n) return;
+  const float* qrow = Q + q * (int64_t)d;
+  for (int j = 0; j < kc; ++j) {
+    int32_t r = cidx[q * kc + j];
+    const bool live = r >= 0 && (int64_t)r < m;
+    if (!live) r = 0;
+    const float* rrow = R + (int64_t)r * d;
+    for (int t = lane; t < d; t += 64) diff[t] = qrow[t] - rrow[t];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    double s = 0.0;
+    for (int u = lane; u < d; u += 64) {
+      double y = 0.0;
+      for (int t = 0; t < d; ++t) y = fma((double)L[(int64_t)t * d + u], (double)diff[t], y);
+      s = fma(y, y, s);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) {
+      cd[j] = live ? (float)sqrt(s) : __builtin_huge_valf();
+      ci[j] = live ? r : 0x7fffffff;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int j = lane; j < kc; j += 64) {
+    const float dj = cd[j];
+    const int32_t rj = ci[j];
+    int rank = 0;
+    for (int i = 0; i < kc; ++i) rank += (cd[i] < dj) || (cd[i] == dj && ci[i] < rj);
+    if (rank < k) {
+      dist[q * k + rank] = dj;
+      idx[q * k + rank] = rj;
+    }
+  }
+}
+
+hipError_t launch_mahalanobis_rerank(const float* Q, const float* R, const float* L, int64_t n, int d, int64_t m,
+                                     const int32_t* cidx, int kc, float* dist, int32_t* idx, int k,
+                                     hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = (size_t)4 * (d + 2 * kc) * 4;
+  if (lds > (size_t)kLdsBytes) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)mahalanobis_rerank_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(mahalanobis_rerank_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), lds, stream, Q, R, L, n, d,
+                     m, cidx, kc, dist, idx, k);
   return hipGetLastError();
 }
 
@@ -533,9 +641,10 @@ hipError_t launch_entropy(const float* dist, const int32_t* idx, int64_t n, int 
 // One wave per row over the concatenated rows of several arrays; a row's
 // job is found by binary search over the jobs' first rows.
 __global__ __launch_bounds__(256) void prep_batched_kernel(const PrepJob* __restrict__ jobs, int njobs,
-                                                           int64_t total_rows) {
+                                                           int64_t total_rows, int* __restrict__ zero) {
   const int lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (zero && g == 0 && lane == 0) *zero = 0;  // item counter of the launch that follows
   if (g >= total_rows) return;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
@@ -570,10 +679,12 @@ __global__ __launch_bounds__(256) void prep_batched_kernel(const PrepJob* __rest
   }
 }
 
-hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream) {
-  if (total_rows <= 0 || njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(prep_batched_kernel, dim3((unsigned)((total_rows + 3) / 4)), dim3(256), 0, stream, jobs_dev, njobs,
-                     total_rows);
+hipError_t launch_prep_batched(const PrepJob* jobs_dev, int njobs, int64_t total_rows, hipStream_t stream,
+                               int* zero) {
+  if ((total_rows <= 0 || njobs <= 0) && !zero) return hipSuccess;
+  const int64_t rows = total_rows > 0 && njobs > 0 ? total_rows : 0;
+  hipLaunchKernelGGL(prep_batched_kernel, dim3((unsigned)std::max<int64_t>(1, (rows + 3) / 4)), dim3(256), 0, stream,
+                     jobs_dev, njobs, rows, zero);
   return hipGetLastError();
 }
 

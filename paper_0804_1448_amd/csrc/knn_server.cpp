@@ -101,15 +101,19 @@ struct Request {
   int status = KNN_OK;
 };
 
-// One launch: requests of one set and one k, queries concatenated.
+// One launch: requests of one set (any k), queries concatenated.  The
+// search keeps k' = max k + s candidates per row; each request's rows are
+// finalized with its own k and k' = k + s, so its result is the one it gets
+// alone.
 struct Batch {
   int set = 0;
-  int k = 0;
+  int k = 0;             // largest k of the batch
   int64_t n = 0;
+  int64_t outs = 0;      // sum of n * k over the requests
   std::vector<Request*> reqs;
   int slot = -1;
   int64_t dev_off = -1;  // arena block
-  int64_t q_bytes = 0, d_bytes = 0, i_bytes = 0, ws_bytes = 0;
+  int64_t q_bytes = 0, d_bytes = 0, i_bytes = 0, t_bytes = 0, ws_bytes = 0;
   Clock::time_point t_ready;  // dry run: completion time
   int64_t seq = 0;            // launch sequence number
   bool launched = false;      // false: failed before reaching the device
@@ -156,8 +160,10 @@ int64_t set_m(const knn_server_s& s, int set) { return s.dry ? s.cfg.dry_m : s.s
 // device bytes of a batch: queries, outputs and the search workspace
 int batch_sizes(knn_server_s& s, Batch& b) {
   b.q_bytes = align_up(b.n * s.d * 4, 256);
-  b.d_bytes = align_up(b.n * b.k * 4, 256);
-  b.i_bytes = align_up(b.n * b.k * 4, 256);
+  b.d_bytes = align_up(b.outs * 4, 256);
+  b.i_bytes = align_up(b.outs * 4, 256);
+  const int nsubs = std::max<int>(1, (int)b.reqs.size());
+  b.t_bytes = (int64_t)sub_tables_bytes(nsubs, b.n);
   if (s.dry) {
     // the workspace a real search of this shape would take
     const int64_t kp = std::min<int64_t>(set_m(s, b.set), b.k + (s.cfg.s_extra < 0 ? 32 : s.cfg.s_extra));
@@ -168,6 +174,7 @@ int batch_sizes(knn_server_s& s, Batch& b) {
   int st = refs_search_args(s.sets[b.set], (const float*)16, b.n, b.k, KNN_L2, s.cfg.precision, s.cfg.s_extra,
                             (float*)16, (int32_t*)16, nullptr, &a);
   if (st != KNN_OK) return st;
+  a.nsubs = nsubs;
   size_t need = 0;
   st = run_search_ws(a, nullptr, 0, &need);
   if (st != KNN_OK) return st;
@@ -176,7 +183,10 @@ int batch_sizes(knn_server_s& s, Batch& b) {
 }
 
 int64_t batch_dev_bytes(const Batch& b) { return b.q_bytes + b.d_bytes + b.i_bytes + b.ws_bytes; }
-int64_t batch_pin_bytes(const Batch& b) { return b.q_bytes + b.d_bytes + b.i_bytes; }
+int64_t batch_pin_bytes(const Batch& b) { return b.q_bytes + b.d_bytes + b.i_bytes + b.t_bytes; }
+
+// extra candidates of the server's searches
+int server_extra(const knn_server_s& s) { return s.cfg.s_extra < 0 ? (s.cfg.precision == KNN_FP32 ? 8 : 32) : s.cfg.s_extra; }
 
 // Grow slot's pinned staging to hold `bytes` (the slot is idle).
 int ensure_pinned(knn_server_s& s, int slot, int64_t bytes) {
@@ -192,7 +202,9 @@ int ensure_pinned(knn_server_s& s, int slot, int64_t bytes) {
   return KNN_OK;
 }
 
-// Launch batch b on its stream (called with the lock held).
+// Launch batch b on its stream.  Called without the lock: the batch owns its
+// slot (stream, staging) and arena block, and reads only the immutable parts
+// of its requests.
 int launch(knn_server_s& s, Batch& b) {
   if (s.dry) {
     const double us = s.cfg.dry_us_per_query * (double)b.n;
@@ -215,12 +227,28 @@ int launch(knn_server_s& s, Batch& b) {
   }
   hipStream_t st = s.streams[b.slot];
   HIP_TRY(hipMemcpyAsync(qd, qp, (size_t)b.n * s.d * 4, hipMemcpyHostToDevice, st), "server H2D");
+  // one finalize instance per request: rows row0.. with the request's own k
+  const int64_t m = s.sets[b.set]->m;
+  const int extra = server_extra(s);
+  std::vector<SubSearch> subs;
+  subs.reserve(b.reqs.size());
+  int64_t row0 = 0, out0 = 0;
+  for (Request* r : b.reqs) {
+    subs.push_back(SubSearch{row0, r->n, r->k, (int)std::min<int64_t>(m, (int64_t)r->k + extra), dd + out0, id + out0});
+    row0 += r->n;
+    out0 += r->n * r->k;
+  }
   SearchArgs a;
   rc = refs_search_args(s.sets[b.set], qd, b.n, b.k, KNN_L2, s.cfg.precision, s.cfg.s_extra, dd, id, st, &a);
-  if (rc == KNN_OK) rc = run_search_ws(a, ws, (size_t)b.ws_bytes, nullptr);
+  if (rc == KNN_OK) {
+    a.subs = subs.data();
+    a.nsubs = (int)subs.size();
+    a.tables_host = pin + b.q_bytes + b.d_bytes + b.i_bytes;
+    rc = run_search_ws(a, ws, (size_t)b.ws_bytes, nullptr);
+  }
   if (rc != KNN_OK) return rc;
-  HIP_TRY(hipMemcpyAsync(pin + b.q_bytes, dd, (size_t)b.n * b.k * 4, hipMemcpyDeviceToHost, st), "server D2H");
-  HIP_TRY(hipMemcpyAsync(pin + b.q_bytes + b.d_bytes, id, (size_t)b.n * b.k * 4, hipMemcpyDeviceToHost, st),
+  HIP_TRY(hipMemcpyAsync(pin + b.q_bytes, dd, (size_t)b.outs * 4, hipMemcpyDeviceToHost, st), "server D2H");
+  HIP_TRY(hipMemcpyAsync(pin + b.q_bytes + b.d_bytes, id, (size_t)b.outs * 4, hipMemcpyDeviceToHost, st),
           "server D2H");
   HIP_TRY(hipEventRecord(s.events[b.slot], st), "server event");
   return KNN_OK;
@@ -235,34 +263,93 @@ bool batch_finished(knn_server_s& s, Batch& b) {
   return true;
 }
 
-// Copy results to the requests' host arrays and release the batch's memory
-// (called with the lock held).
-void complete(knn_server_s& s, Batch& b) {
-  const Clock::time_point now = Clock::now();
-  int64_t row = 0;
+// Copy a finished batch's results to its requests' host arrays.  Called
+// without the lock: the requests are still on the device as far as every
+// other thread can tell, so nothing else touches their arrays.
+void copy_results(knn_server_s& s, Batch& b) {
+  int64_t out0 = 0;
   const unsigned char* pin = s.dry ? nullptr : (const unsigned char*)s.pinned[b.slot];
   for (Request* r : b.reqs) {
-    const int64_t cnt = r->n * (int64_t)b.k;
+    const int64_t cnt = r->n * (int64_t)r->k;
     if (s.dry) {
       for (int64_t e = 0; e < cnt; ++e) {
         r->dist[e] = (float)b.set;
         r->idx[e] = (int32_t)(b.seq & 0x7fffffff);
       }
     } else if (b.status == KNN_OK) {
-      memcpy(r->dist, pin + b.q_bytes + row * b.k * 4, (size_t)cnt * 4);
-      memcpy(r->idx, pin + b.q_bytes + b.d_bytes + row * b.k * 4, (size_t)cnt * 4);
+      memcpy(r->dist, pin + b.q_bytes + out0 * 4, (size_t)cnt * 4);
+      memcpy(r->idx, pin + b.q_bytes + b.d_bytes + out0 * 4, (size_t)cnt * 4);
     }
-    row += r->n;
+    out0 += cnt;
+  }
+}
+
+// Mark a batch's requests done and release its memory and slot (lock held).
+void complete(knn_server_s& s, Batch& b) {
+  const Clock::time_point now = Clock::now();
+  for (Request* r : b.reqs) {
     r->status = b.status;
     r->state = 2;
     r->t_done = now;
   }
   s.stats.completed += (int64_t)b.reqs.size();
-  s.dev_arena->release(b.dev_off);
+  if (b.dev_off >= 0) s.dev_arena->release(b.dev_off);
   s.slot_busy[b.slot] = false;
 }
 
+// A request that heads the queue but waits for arena memory lets later
+// requests that fit go ahead of it for at most this long; after that nothing
+// passes it until memory frees up.
+constexpr auto kHeadBypass = std::chrono::milliseconds(50);
+
+// The batch headed by waiting request `hi`: it and later waiting requests of
+// its set, up to max_batch_queries, cut back until the batch's memory fits
+// the arena.  nullptr when even the head alone does not fit (lock held).
+std::unique_ptr<Batch> try_batch(knn_server_s& s, size_t hi, int slot) {
+  Request* head = s.waiting[hi];
+  std::vector<Request*> cand{head};
+  int64_t n = head->n;
+  for (size_t i = hi + 1; i < s.waiting.size(); ++i) {
+    Request* r = s.waiting[i];
+    if (r->set == head->set && n + r->n <= s.cfg.max_batch_queries) {
+      cand.push_back(r);
+      n += r->n;
+    }
+  }
+  while (!cand.empty()) {
+    auto b = std::make_unique<Batch>();
+    b->set = head->set;
+    b->reqs = cand;
+    for (Request* r : cand) {
+      b->n += r->n;
+      b->k = std::max(b->k, r->k);
+      b->outs += r->n * (int64_t)r->k;
+    }
+    const int st = batch_sizes(s, *b);
+    const int64_t dev_off = st == KNN_OK ? s.dev_arena->alloc(batch_dev_bytes(*b)) : -1;
+    if (dev_off < 0 && st == KNN_OK) {
+      if (cand.size() == 1) return nullptr;  // the head does not fit yet
+      cand.pop_back();
+      continue;
+    }
+    // (a head that cannot be planned fails without a launch: status set)
+    b->status = st;
+    b->dev_off = dev_off;
+    b->slot = slot;
+    for (Request* r : cand) {
+      r->state = 1;
+      s.waiting.erase(std::find(s.waiting.begin(), s.waiting.end(), r));
+    }
+    s.slot_busy[slot] = true;
+    return b;
+  }
+  return nullptr;
+}
+
 // Form the next batch from the waiting queue, or return nullptr (lock held).
+// The oldest waiting request heads it; if that one waits for memory, the
+// next requests in arrival order may head a batch instead, until the oldest
+// has waited kHeadBypass.
 std::unique_ptr<Batch> form_batch(knn_server_s& s) {
   if (s.waiting.empty()) return nullptr;
   int slot = -1;
@@ -272,47 +359,13 @@ std::unique_ptr<Batch> form_batch(knn_server_s& s) {
       break;
     }
   if (slot < 0) return nullptr;
-  Request* head = s.waiting.front();
-  // candidates: the head, then later waiting requests of the same set and k
-  std::vector<Request*> cand{head};
-  int64_t n = head->n;
-  for (size_t i = 1; i < s.waiting.size(); ++i) {
-    Request* r = s.waiting[i];
-    if (r->set == head->set && r->k == head->k && n + r->n <= s.cfg.max_batch_queries) {
-      cand.push_back(r);
-      n += r->n;
-    }
+  const bool may_bypass = Clock::now() - s.waiting.front()->t_submit < kHeadBypass;
+  for (size_t hi = 0; hi < s.waiting.size(); ++hi) {
+    if (hi > 0 && !may_bypass) break;
+    std::unique_ptr<Batch> b = try_batch(s, hi, slot);
+    if (b) return b;
   }
-  // largest prefix of the candidates whose memory fits the arena
-  while (!cand.empty()) {
-    auto b = std::make_unique<Batch>();
-    b->set = head->set;
-    b->k = head->k;
-    for (Request* r : cand) b->n += r->n;
-    const int st = batch_sizes(s, *b);
-    const int64_t dev_off = st == KNN_OK ? s.dev_arena->alloc(batch_dev_bytes(*b)) : -1;
-    if (dev_off < 0 && cand.size() > 1) {
-      cand.pop_back();
-      continue;
-    }
-    if (st != KNN_OK) {
-      // the head alone cannot be planned: it fails without a launch
-      b->status = st;
-      b->reqs = cand;
-    } else if (dev_off < 0) {
-      return nullptr;  // the head does not fit yet: wait for memory
-    }
-    b->dev_off = dev_off;
-    b->slot = slot;
-    b->reqs = cand;
-    for (Request* r : cand) {
-      r->state = 1;
-      s.waiting.erase(std::find(s.waiting.begin(), s.waiting.end(), r));
-    }
-    s.slot_busy[slot] = true;
-    return b;
-  }
-  return nullptr;  // the head does not fit yet: wait for memory
+  return nullptr;
 }
 
 void engine_loop(knn_server_s* s) {
@@ -320,30 +373,39 @@ void engine_loop(knn_server_s* s) {
   std::unique_lock<std::mutex> lock(s->mu);
   for (;;) {
     bool progressed = false;
-    // completions
+    // completions: results are copied to the host arrays outside the lock
+    std::vector<std::unique_ptr<Batch>> finished;
     for (size_t i = 0; i < s->running.size();) {
       if (batch_finished(*s, *s->running[i])) {
-        complete(*s, *s->running[i]);
+        finished.push_back(std::move(s->running[i]));
         s->running.erase(s->running.begin() + (long)i);
-        progressed = true;
       } else {
         ++i;
       }
     }
-    if (progressed) s->cv_done.notify_all();
-    // admissions
+    if (!finished.empty()) {
+      lock.unlock();
+      for (auto& b : finished) copy_results(*s, *b);
+      lock.lock();
+      for (auto& b : finished) complete(*s, *b);
+      progressed = true;
+      s->cv_done.notify_all();
+    }
+    // admissions: a batch is formed (requests, slot and memory reserved)
+    // under the lock and launched outside it
     for (;;) {
       std::unique_ptr<Batch> b = form_batch(*s);
       if (!b) break;
-      b->seq = s->stats.batches;
+      b->seq = s->stats.batches++;
+      s->stats.queries += b->n;
       if (b->status == KNN_OK) {
+        lock.unlock();
         b->status = launch(*s, *b);
         // a launch that failed part way may have queued work on the stream
         b->launched = b->status == KNN_OK || (!s->dry && hipEventRecord(s->events[b->slot],
                                                                          s->streams[b->slot]) == hipSuccess);
+        lock.lock();
       }
-      ++s->stats.batches;
-      s->stats.queries += b->n;
       s->running.push_back(std::move(b));
       s->stats.peak_batches_in_flight = std::max<int32_t>(s->stats.peak_batches_in_flight, (int32_t)s->running.size());
       s->stats.peak_mem_in_flight = std::max<int64_t>(s->stats.peak_mem_in_flight, s->dev_arena->in_use());
@@ -452,6 +514,7 @@ int knn_server_submit(knn_server_t srv, int32_t set, const float* Q_host, int64_
     probe.set = set;
     probe.k = k;
     probe.n = n;
+    probe.outs = n * (int64_t)k;
     std::lock_guard<std::mutex> lock(srv->mu);
     st = batch_sizes(*srv, probe);
     if (st != KNN_OK) return st;

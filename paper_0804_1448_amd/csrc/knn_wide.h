@@ -37,7 +37,6 @@ constexpr int kWideWaves = 8;
 constexpr int kWideQueriesPerWave = 32;
 constexpr int kWideQueriesWG = kWideWaves * kWideQueriesPerWave;  // queries per workgroup
 static_assert(kWideQueriesWG == kWideQueries, "host and kernel agree on the query block");
-constexpr int kWideMaxKeys = 64;                              // list capacity: one key per lane
 
 // Minimum of three scores with v_min3_f32 as it stands.  The scores come from
 // matrix instructions or are the quiet NaN that marks rows past the end of
@@ -49,41 +48,51 @@ __device__ __forceinline__ float min3_raw(float a, float b, float c) {
   return r;
 }
 
+// Geometry of one instantiation (KIND, NKG).
+template <int KIND, int NKG>
+struct WideGeom {
+  static constexpr bool F32 = KIND == TILE_L2_F32;
+  static constexpr int ES = F32 ? 4 : 2;                 // element bytes
+  static constexpr int STAGES = F32 ? 2 : 3;             // tiles in flight
+  static constexpr int SUB = F32 ? 16 : 24;              // keys per lane segment
+  static constexpr int SEG = SUB + 1;                    // padded against bank conflicts
+  static constexpr int VPR = NKG * 16 * ES / 16;         // 16-byte slots of a row's data
+  static constexpr int RS = VPR + 1;                     // slots per staged row: data + one pad slot
+  static constexpr int TILE_BYTES = kStepRefs * RS * 16; // 64 references
+  static constexpr int TILES_LDS = STAGES * TILE_BYTES;
+  static constexpr int NORMS_LDS = STAGES * kStepRefs;   // floats
+  static constexpr int BUFS_LDS = kWideWaves * 64 * SEG; // keys
+};
+
+// One work item of the kernel: the queries of block `qblock` of instance
+// `in` against reference slice `slice`, with lists of up to 64 * LK keys
+// (LK = 1: k' <= 64; LK = 2: k' <= 128, 16-bit tiles only).  The LDS arrays
+// are the caller's (sized by WideGeom); the item leaves no state behind in
+// them that a later item reads.
 // NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG; even
 // for the 16-bit kinds, whose rows are padded to 32).
-template <int KIND, int NKG>
-__global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
+template <int KIND, int NKG, int LK>
+__device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int slice, unsigned char* tiles,
+                                          float* norms, uint64_t* bufs) {
   static_assert(KIND == TILE_L2_F32 || KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "Euclidean tiles only");
-  constexpr bool F32 = KIND == TILE_L2_F32;
+  using G = WideGeom<KIND, NKG>;
+  constexpr bool F32 = G::F32;
   static_assert(NKG >= 1 && NKG <= 8 && (F32 || NKG % 2 == 0), "dp <= 128");
-  constexpr int ES = F32 ? 4 : 2;                    // element bytes
-  constexpr int STAGES = F32 ? 2 : 3;                // tiles in flight
-  constexpr int SUB = F32 ? 16 : 24;                 // keys per lane segment
-  constexpr int SEG = SUB + 1;                       // padded against bank conflicts
-  constexpr int VPR = NKG * 16 * ES / 16;            // 16-byte slots of a row's data
+  static_assert(LK == 1 || (LK == 2 && !F32), "two keys per lane for the 16-bit kinds only");
+  constexpr int ES = G::ES;
+  constexpr int STAGES = G::STAGES;
+  constexpr int SUB = G::SUB;
+  constexpr int SEG = G::SEG;
+  constexpr int VPR = G::VPR;
   constexpr int NU = VPR / 2;                        // slot pairs: a lane half reads one slot of each
-  constexpr int RS = VPR + 1;                        // slots per staged row: data + one pad slot
-  constexpr int TILE_BYTES = kStepRefs * RS * 16;    // 64 references
+  constexpr int RS = G::RS;
+  constexpr int TILE_BYTES = G::TILE_BYTES;
   constexpr int NI = RS;                             // wave-wide copy instructions per tile
   constexpr int PER_WAVE = (NI + kWideWaves - 1) / kWideWaves;
   constexpr int VM_PER_STAGE = PER_WAVE + 1;         // tile slots + norms, per wave
 
-  __shared__ __align__(16) unsigned char tiles[STAGES * TILE_BYTES];
-  __shared__ __align__(16) float norms[STAGES * kStepRefs];
-  __shared__ __align__(16) uint64_t bufs[kWideWaves * 64 * SEG];
-
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, c = lane & 31, h = lane >> 5;
-  int qblock = blockIdx.x, slice = blockIdx.y;
-  FusedInst in;
-  if (p.items) {
-    const FusedItem it = p.items[blockIdx.x];
-    in = p.insts[it.inst];
-    qblock = it.qblock;
-    slice = it.slice;
-  } else {
-    in = p.one;
-  }
   const int64_t q0 = (int64_t)qblock * kWideQueriesWG + wave * kWideQueriesPerWave;
   const int64_t qrow = q0 + c;
   const int64_t qsafe = qrow < in.n ? qrow : in.n - 1;
@@ -157,11 +166,16 @@ __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
   };
 
   // ---- selection state
-  u32x32 Llo, Lhi;  // list key e of query j: lane e of register pair j
+  u32x32 Llo, Lhi;    // list key e of query j: lane e of register pair j
+  u32x32 Llo2, Lhi2;  // LK = 2: list key 64 + e of query j
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     Llo[j] = 0xffffffffu;
     Lhi[j] = 0xffffffffu;
+    if constexpr (LK == 2) {
+      Llo2[j] = 0xffffffffu;
+      Lhi2[j] = 0xffffffffu;
+    }
   }
   float thr = __builtin_huge_valf();
   int lcnt = 0;
@@ -183,10 +197,29 @@ __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
       const uint64_t l = ((uint64_t)Lhi[j] << 32) | Llo[j];
       x = bitonic_sort64(x, lane, true);
       uint64_t m = l < x ? l : x;
-      m = bitonic_clean64(m, lane);
+      uint32_t kth;
+      if constexpr (LK == 1) {
+        m = bitonic_clean64(m, lane);
+        kth = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), kc - 1);
+      } else {
+        // list = A (keys 0..63) then B (64..127), both ascending; x descending.
+        // min(A, x) holds the 64 smallest of A and x, max(A, x) the rest,
+        // both bitonic.  Every key of min(A, x) is at most max(A) <= min(B),
+        // so the new list is sort(min(A, x)) followed by the 64 smallest of
+        // max(A, x) and B.
+        uint64_t hi = l < x ? x : l;
+        m = bitonic_clean64(m, lane);
+        hi = bitonic_clean64_desc(hi, lane);
+        const uint64_t b = ((uint64_t)Lhi2[j] << 32) | Llo2[j];
+        uint64_t m2 = b < hi ? b : hi;
+        m2 = bitonic_clean64(m2, lane);
+        Llo2[j] = (uint32_t)m2;
+        Lhi2[j] = (uint32_t)(m2 >> 32);
+        kth = kc > 64 ? (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m2 >> 32), kc - 65)
+                      : (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), kc - 1);
+      }
       Llo[j] = (uint32_t)m;
       Lhi[j] = (uint32_t)(m >> 32);
-      const uint32_t kth = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32), kc - 1);
       if (c == j) {
         lcnt = 0;
         thr = kth == 0xffffffffu ? __builtin_huge_valf() : mono_value(kth);
@@ -337,6 +370,84 @@ __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
     const int64_t qg = q0 + j;
     if (qg < in.n && lane < kc)
       in.part[(qg * in.P + slice) * kc + lane] = ((uint64_t)Lhi[j] << 32) | Llo[j];
+    if constexpr (LK == 2)
+      if (qg < in.n && lane + 64 < kc)
+        in.part[(qg * in.P + slice) * kc + 64 + lane] = ((uint64_t)Lhi2[j] << 32) | Llo2[j];
+  }
+}
+
+// One instance per launch: grid (query blocks, slices) of p.one, or one item
+// of p.items per workgroup.
+template <int KIND, int NKG>
+__global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
+  using G = WideGeom<KIND, NKG>;
+  __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
+  __shared__ __align__(16) float norms[G::NORMS_LDS];
+  __shared__ __align__(16) uint64_t bufs[G::BUFS_LDS];
+  if (p.items) {
+    const FusedItem it = p.items[blockIdx.x];
+    const FusedInst in = p.insts[it.inst];
+    wide_item<KIND, NKG, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+  } else {
+    wide_item<KIND, NKG, 1>(p.one, blockIdx.x, blockIdx.y, tiles, norms, bufs);
+  }
+}
+
+// The same with two keys per lane (k' <= 128; 16-bit tiles).
+template <int KIND, int NKG>
+__global__ __launch_bounds__(512) void wide2_kernel(FusedParams p) {
+  using G = WideGeom<KIND, NKG>;
+  __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
+  __shared__ __align__(16) float norms[G::NORMS_LDS];
+  __shared__ __align__(16) uint64_t bufs[G::BUFS_LDS];
+  if (p.items) {
+    const FusedItem it = p.items[blockIdx.x];
+    const FusedInst in = p.insts[it.inst];
+    wide_item<KIND, NKG, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+  } else {
+    wide_item<KIND, NKG, 2>(p.one, blockIdx.x, blockIdx.y, tiles, norms, bufs);
+  }
+}
+
+// Batched form in one launch: 16-bit instances of any padded dimension up
+// to 128 and k' up to 128.  The grid has one workgroup per item; each
+// workgroup takes the next item (instance, query block, slice) in the order
+// of p.items -- longest first -- from the counter p.counter, which the
+// launch before this one on the stream zeroes.  The counter, not the block
+// index, fixes the order in which items start across the dispatchers of
+// the eight XCDs, so the longest items start first device-wide.  Every
+// workgroup takes exactly one item; none waits for another.
+template <int KIND>
+__global__ __launch_bounds__(512) void wide_batch_kernel(FusedParams p) {
+  using G = WideGeom<KIND, 8>;
+  __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
+  __shared__ __align__(16) float norms[G::NORMS_LDS];
+  __shared__ __align__(16) uint64_t bufs[G::BUFS_LDS];
+  __shared__ int taken;
+  if (threadIdx.x == 0) taken = atomicAdd(p.counter, 1);
+  __syncthreads();
+  const int i = __builtin_amdgcn_readfirstlane(taken);  // uniform: item and instance fields in scalar registers
+  if (i >= p.nitems) return;
+  const FusedItem it = p.items[i];
+  const FusedInst in = p.insts[it.inst];
+  const bool two = in.kc > kWideMaxKc1;
+  switch (in.dp) {
+    case 32:
+      if (two) wide_item<KIND, 2, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 2, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      break;
+    case 64:
+      if (two) wide_item<KIND, 4, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 4, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      break;
+    case 96:
+      if (two) wide_item<KIND, 6, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 6, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      break;
+    default:
+      if (two) wide_item<KIND, 8, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 8, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      break;
   }
 }
 
@@ -345,7 +456,20 @@ hipError_t launch_wide_one(const FusedParams& p, hipStream_t stream) {
   if (p.items && p.nitems <= 0) return hipSuccess;
   dim3 grid = p.items ? dim3((unsigned)p.nitems)
                       : dim3((unsigned)((p.one.n + kWideQueriesWG - 1) / kWideQueriesWG), (unsigned)p.one.P);
+  if constexpr (KIND != TILE_L2_F32) {
+    if (p.kc_max > kWideMaxKc1) {
+      hipLaunchKernelGGL((wide2_kernel<KIND, NKG>), grid, dim3(kWideWaves * kWaveSize), 0, stream, p);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((wide_kernel<KIND, NKG>), grid, dim3(kWideWaves * kWaveSize), 0, stream, p);
+  return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_wide_batch_one(const FusedParams& p, hipStream_t stream) {
+  if (p.nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL((wide_batch_kernel<KIND>), dim3((unsigned)p.nitems), dim3(kWideWaves * kWaveSize), 0, stream, p);
   return hipGetLastError();
 }
 

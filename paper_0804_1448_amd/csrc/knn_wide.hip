@@ -1,6 +1,7 @@
 // knn_wide.hip -- instantiations of the 32x32-tile Euclidean kernel with
 // register-resident lists (knn_wide.h): 16-bit tiles for dp = 32, 64, 96,
-// 128; float32 tiles for dp = 16..128.
+// 128 and k' <= 128 (one or two list keys per lane), also as the one-launch
+// batched kernel; float32 tiles for dp = 16..128 and k' <= 64.
 #include "knn_wide.h"
 
 namespace knn {
@@ -31,7 +32,14 @@ static hipError_t dispatch_f32(const FusedParams& p, hipStream_t stream) {
 }
 
 hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream) {
-  if (kind == TILE_L2_F32) return dispatch_f32(p, stream);
+  if (kind == TILE_L2_F32) return p.kc_max <= kWideMaxKc1 ? dispatch_f32(p, stream) : hipErrorInvalidValue;
+  if (p.kc_max > kWideMaxKc) return hipErrorInvalidValue;
+  if (p.counter) {
+    if (!p.items) return hipErrorInvalidValue;
+    if (kind == TILE_L2_BF16) return launch_wide_batch_one<TILE_L2_BF16>(p, stream);
+    if (kind == TILE_L2_F16) return launch_wide_batch_one<TILE_L2_F16>(p, stream);
+    return hipErrorInvalidValue;
+  }
   if (kind == TILE_L2_BF16) return dispatch_half<TILE_L2_BF16>(p, stream);
   if (kind == TILE_L2_F16) return dispatch_half<TILE_L2_F16>(p, stream);
   return hipErrorInvalidValue;

@@ -118,3 +118,18 @@ def test_batch_create_rejects_bad_arguments(lib):
     assert lib.knn_batch_run(None, 0, None) == -1
     assert lib.knn_batch_destroy(None) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("metric", [0, 1, 2])
+@pytest.mark.parametrize("d", [1, 3, 96, 129, 512])
+def test_k_limit_is_the_documented_one(lib, metric, d):
+    """k' = k + 8 <= 448 for knn_search: k = 440 is planned (on a machine
+    without a GPU the call then stops at the first device call with
+    KNN_ERR_DEVICE, before any launch), k = 441 is rejected as unsupported
+    before any device call; with m <= 448 every k <= m is planned."""
+    P = ctypes.c_void_p
+    F = P(0x1000)
+    assert lib.knn_search(F, 64, F, 100000, d, 440, metric, F, F, None) != -2
+    assert lib.knn_search(F, 64, F, 100000, d, 441, metric, F, F, None) == -2
+    assert "448" in lib.knn_last_error().decode() or "449" in lib.knn_last_error().decode()
+    assert lib.knn_search(F, 64, F, 448, d, 448, metric, F, F, None) != -2

@@ -98,6 +98,41 @@ def test_batched_equals_single_and_oracle(K, precision, metrics):
         it["refs"].close()
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_batched_one_launch_equals_per_group_launches(K, precision):
+    """All 16-bit instances with k' <= 128 and d <= 128 run in one launch of
+    the 32x32-tile kernel (one workgroup per item, items taken longest first
+    through a counter).  Its results must equal, bit for bit, those of
+    per-group launches (KNN_BATCH_ONE=-1) and of single searches, for every
+    padded width and for lists of one and two keys per lane."""
+    import os
+
+    banner(f"batched one launch {precision}")
+    inst = make_instances(5, 20, ["l2"], precision, dims=(16, 32, 48, 64, 100, 128), ks=(1, 8, 32, 60, 100))
+    probs = [(it["refs"], it["Qd"], it["k"], it["metric"]) for it in inst]
+    want = []
+    for it in inst:
+        d_, i_ = it["refs"].search(it["Qd"], it["k"], "l2", precision=precision, s_extra=28)
+        want.append((d_.cpu().numpy(), i_.cpu().numpy()))
+    one = as_np(K.search_batched(probs, precision, s_extra=28))
+    os.environ["KNN_BATCH_ONE"] = "-1"
+    try:
+        per_group = as_np(K.search_batched(probs, precision, s_extra=28))
+    finally:
+        del os.environ["KNN_BATCH_ONE"]
+    hits = slots = 0.0
+    for j, (it, (wd, wi), (od, oi), (gd, gi)) in enumerate(zip(inst, want, one, per_group)):
+        assert np.array_equal(wd, od) and np.array_equal(wi, oi), f"instance {j}: one launch vs single"
+        assert np.array_equal(gd, od) and np.array_equal(gi, oi), f"instance {j}: one launch vs per group"
+        rep = compare(it["Q"], it["R"], it["k"], "l2", od, oi, tol=TOL)
+        assert rep["bad_index_rows"] == 0 and rep["bad_pair"] == 0 and rep["max_rel_err_hits"] <= TOL, (j, rep)
+        hits += rep["recall"] * rep["queries"] * rep["k"]
+        slots += rep["queries"] * rep["k"]
+    assert hits / slots >= 0.999, hits / slots
+    for it in inst:
+        it["refs"].close()
+
+
 def test_batched_large_k_and_ragged(K):
     """k' above 64 takes the rank merge; instances with n = 1, m = k and n not a multiple of 16."""
     import torch

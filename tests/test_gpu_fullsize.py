@@ -125,7 +125,9 @@ def test_batched_form_full_size(K):
         refs = K.Refs(torch.from_numpy(R).cuda(), storage="fp16", keep_fp32_master=True)
         probs.append((refs, torch.from_numpy(Q).cuda(), k, "l2"))
         keep.append(refs)
-    b = K.Batch(probs, "fp16", tune=True)
+    # k + 28 <= 128 keeps every instance (k up to 100) in the one launch of
+    # the 32x32-tile kernel
+    b = K.Batch(probs, "fp16", s_extra=28, tune=True)
     try:
         b.run()
         for _ in range(2):

@@ -84,11 +84,48 @@ def test_mahalanobis_matches_oracle(K, n, m, d, k, kind):
 
 
 def test_identity_equals_euclidean(K):
+    """Sigma = I: the Mahalanobis search returns the Euclidean search's
+    neighbours (exactly where the oracle separates consecutive neighbours by
+    more than 1e-6) and distances within 1e-6."""
     import torch
+
+    import oracle
 
     banner("mahalanobis identity")
     Q, R = synthdata.uniform((200, 24), 970, 1), synthdata.uniform((3000, 24), 970, 0)
     a = run(K, Q, R, np.eye(24), 15)
     b = [t.cpu().numpy() for t in K.search(torch.from_numpy(Q).cuda(), torch.from_numpy(R).cuda(), 15, "l2")]
-    assert np.array_equal(a[1], b[1])
+    D, _ = oracle.knn(Q, R, 16, "l2")
+    separated = np.all(np.diff(D, axis=1) > 1e-6 * D[:, 1:], axis=1)
+    assert separated.mean() > 0.9
+    assert np.array_equal(a[1][separated], b[1][separated])
     assert np.allclose(a[0], b[0], rtol=1e-6, atol=0)
+
+
+def test_clustered_data(K):
+    """Tight clusters (sigma = 0.01) far from the set's centre: neighbours
+    are 30x closer to each other than to the centre, which the exact re-rank
+    from the caller's rows must not feel."""
+    banner("mahalanobis clustered")
+    d = 32
+    Q = synthdata.gmm(200, d, 64, 0.01, 980, 1)
+    R = synthdata.gmm(20000, d, 64, 0.01, 980, 0)
+    L = factor(d, 981, "general")
+    check(Q, R, L, 10, *run(K, Q, R, L, 10))
+
+
+def test_near_duplicates(K):
+    """Queries 1e-5 from a reference and references 1e-6 from one another:
+    distances of order 1e-5 next to coordinates of order 1 must still come
+    out within relative 1e-5."""
+    banner("mahalanobis near duplicates")
+    d = 24
+    R = synthdata.gmm(5000, d, 16, 0.05, 985, 0)
+    rng = synthdata.rng_for(985, synthdata.ROLE_EXTRA)
+    dup = rng.choice(5000, 500, replace=False)
+    R[dup[:250]] = R[dup[250:]] + (1e-6 * rng.standard_normal((250, d))).astype(np.float32)
+    Q = (R[dup[250:350]] + 1e-5 * rng.standard_normal((100, d))).astype(np.float32)
+    L = factor(d, 986, "general")
+    dist, idx = run(K, Q, R, L, 8)
+    assert np.all(dist[:, 0] < 1e-3)
+    check(Q, R, L, 8, dist, idx)

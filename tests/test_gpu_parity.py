@@ -230,3 +230,49 @@ def test_errors_leave_outputs_untouched(K):
     with pytest.raises(K.KnnError):
         refs16.search(Q, 2, "l1", precision="bf16")
     refs16.close()
+
+
+@pytest.mark.parametrize("metric,storage,prec,k", [("l2", None, None, 20), ("l1", None, None, 20),
+                                                   ("linf", None, None, 5), ("l2", "bf16", "bf16", 32),
+                                                   ("l2", "fp16", "fp16", 50)])
+def test_many_slices_merged_first(K, metric, storage, prec, k):
+    """A few queries against many references: the search spreads over more
+    slices than the finalize merges at once (up to 256), so the slice lists
+    are merged in groups first.  The result must match the oracle and equal,
+    bit for bit, the search with at most 64 slices (KNN_FUSED_P=16), whose
+    lists the finalize merges directly: the kept top-k' under the (score,
+    index) order does not depend on the slicing."""
+    n, m, d = 37, 400000, 48
+    banner(f"many slices {metric} {prec} k={k}: n={n} m={m} d={d}")
+    Q, R = make_data("gmm", n, m, d, 4242)
+    a = gpu_search(K, Q, R, k, metric, refs_storage=storage, precision=prec)
+    os.environ["KNN_FUSED_P"] = "16"
+    try:
+        b = gpu_search(K, Q, R, k, metric, refs_storage=storage, precision=prec)
+    finally:
+        del os.environ["KNN_FUSED_P"]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    rep = compare(Q, R, k, metric, a[0], a[1], tol=TOL)
+    if prec is None:
+        assert rep["ok"], rep
+    else:
+        assert rep["bad_index_rows"] == 0 and rep["bad_pair"] == 0 and rep["recall"] >= 0.999, rep
+
+
+@pytest.mark.parametrize("metric", ["l2", "l1"])
+def test_k_at_the_limit_and_above(K, metric):
+    """k = 440 (k' = 448, the most candidates the fused kernels keep) matches
+    the oracle; k = 441 is rejected as unsupported with the outputs untouched."""
+    import torch
+
+    banner(f"k limit {metric}")
+    Q, R = make_data("uniform", 100, 6000, 24, 4401)
+    dist, idx = gpu_search(K, Q, R, 440, metric)
+    assert_parity(Q, R, 440, metric, dist, idx)
+    Qd, Rd = torch.from_numpy(Q).cuda(), torch.from_numpy(R).cuda()
+    out = (torch.full((100, 441), -5.0, device="cuda"), torch.full((100, 441), -5, dtype=torch.int32, device="cuda"))
+    with pytest.raises(K.KnnError) as e:
+        K.search(Qd, Rd, 441, metric, out=out)
+    assert e.value.status == -2
+    torch.cuda.synchronize()
+    assert bool((out[0] == -5.0).all()) and bool((out[1] == -5).all())

@@ -170,3 +170,36 @@ def test_wide_fp32_matches_oracle_and_general(K, n, m, d, k):
     for dist, idx in (a, b, c):
         rep = compare(Q, R, k, "l2", dist, idx, tol=TOL, ref=ref, rows=rows)
         assert rep["ok"], rep
+
+
+# k' = k + s in (64, 128]: two list keys per lane
+SHAPES_TWO_KEYS = [
+    (129, 3000, 64, 50, 32, "fp16", "gmm"),       # k' = 82
+    (300, 20000, 128, 96, 32, "bf16", "gmm"),     # k' = 128
+    (70, 50000, 32, 100, 28, "fp16", "uniform"),  # k' = 128
+    (257, 1000, 96, 65, 1, "bf16", "uniform"),    # k' = 66
+    (33, 100, 16, 80, 32, "fp16", "uniform"),     # k' = 100 of m = 100
+]
+
+
+@pytest.mark.parametrize("n,m,d,k,s,prec,kind", SHAPES_TWO_KEYS)
+def test_wide_two_keys_per_lane(K, n, m, d, k, s, prec, kind):
+    banner(f"wide two keys n={n} m={m} d={d} k={k} s={s} {prec} {kind}")
+    Q, R = data(kind, n, m, d, 500 + d + k)
+    dist, idx = search16(K, Q, R, k, prec, s_extra=s)
+    check(Q, R, k, dist, idx)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_wide_two_keys_integer_grid_is_exact(K, prec):
+    """The integer-grid case of test_wide_integer_grid_is_exact with k' = 128
+    (k = 96): the two-register lists must reproduce the oracle bit for bit."""
+    banner(f"wide two keys integer grid {prec}")
+    Q = synthdata.integer_grid((300, 64), 0, 6, 89, 1)
+    R = synthdata.integer_grid((9000, 64), 0, 6, 89, 0)
+    R[128:256] = 5.0 - R[0:128]
+    k = 96
+    dist, idx = search16(K, Q, R, k, prec, s_extra=32)
+    D, I = oracle.knn(Q, R, k, "l2")
+    assert np.array_equal(idx, I.astype(np.int32))
+    assert np.array_equal(dist, D.astype(np.float32))

@@ -53,7 +53,7 @@ def test_routing_and_results_shape(K):
         assert st["queries"] == sum(n for _, _, n, _ in subs)
 
 
-def test_batch_mates_share_set_and_k_and_respect_max_queries(K):
+def test_batch_mates_share_set_and_respect_max_queries(K):
     maxq = 40
     with K.Server.dry(2, m=500, d=D, us_per_query=200.0, max_batches=1, max_batch_queries=maxq) as srv:
         # the first request occupies the only stream; the rest queue up behind it
@@ -66,11 +66,15 @@ def test_batch_mates_share_set_and_k_and_respect_max_queries(K):
         by_batch = {}
         for t, s, n, k in subs:
             by_batch.setdefault(int(res[t][1][0, 0]), []).append((s, n, k))
+        mixed_k = 0
         for b, members in by_batch.items():
-            assert len({(s, k) for s, _, k in members}) == 1, (b, members)
+            assert len({s for s, _, _ in members}) == 1, (b, members)
             assert sum(n for _, n, _ in members) <= maxq
-        # queued requests were batched: far fewer launches than requests
-        assert len(by_batch) < len(subs) / 2
+            mixed_k += len({k for _, _, k in members}) > 1
+        # queued requests were batched: far fewer launches than requests, and
+        # requests of different k share launches
+        assert len(by_batch) < len(subs) / 3
+        assert mixed_k > 0
         assert srv.stats()["batches"] == len(by_batch)
 
 
@@ -97,6 +101,26 @@ def test_other_set_is_not_starved_by_a_stream_of_mates(K):
         # predecessors head; at most the first four requests' batches precede it
         assert b_lone <= b_first + 1
         assert b_lone <= 4
+
+
+def test_small_request_passes_a_head_waiting_for_memory(K):
+    """A request too large for the memory left waits; a later small one that
+    fits launches meanwhile (for at most 50 ms of the large one's wait)."""
+    probe = K.Server.dry(1, m=2000, d=D, us_per_query=0.0, mem_budget=1 << 40)
+    probe.wait(probe.submit(0, q(200), 16))
+    one = probe.stats()["peak_mem_in_flight"]
+    probe.close()
+    with K.Server.dry(2, m=2000, d=D, us_per_query=100.0, mem_budget=int(one * 1.6), max_batches=4,
+                      max_batch_queries=256) as srv:
+        first = srv.submit(0, q(200, 1), 16)       # 20 ms on the device, most of the memory
+        deadline = time.time() + 5
+        while srv.stats()["batches"] < 1 and time.time() < deadline:
+            time.sleep(0.0005)
+        big = srv.submit(1, q(200, 2), 16)         # does not fit next to the first
+        small = srv.submit(1, q(4, 3), 16)         # fits: goes ahead of `big`
+        res = wait_all(srv, [first, big, small])
+        assert int(res[small][1][0, 0]) < int(res[big][1][0, 0])
+        assert srv.stats()["peak_mem_in_flight"] <= int(one * 1.6)
 
 
 def test_memory_budget_bounds_batches_in_flight(K):
