@@ -98,6 +98,27 @@ int knn_search(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, 
                int32_t metric, float* dist, int32_t* idx, void* stream);
 
 /*
+ * knn_search_noalloc -- knn_search for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as knn_search, and
+ * the same kernels; the workspace (prepared rows, half norms, per-slice
+ * candidate lists) is a fixed array of KNN_NOALLOC_MAX_BYTES in the
+ * library's device memory, one per device, held until the process ends.
+ * The call allocates nothing: no hipMalloc, no hipFree, no event.
+ *   A search whose workspace exceeds KNN_NOALLOC_MAX_BYTES returns
+ *   KNN_ERR_UNSUPPORTED before anything is enqueued (the workspace of
+ *   knn_search is about 4 (m + n) d + 8 n P k' bytes, P <= 256 slices,
+ *   k' = min(m, k + 8); the 16384 x 16384 x 96, k = 20 search needs 29 MB).
+ *   Every call on one device shares that device's array: calls that may
+ *   overlap on one device (on different streams, or from different threads
+ *   on one stream) race and corrupt each other's results; the caller
+ *   orders them.  No buffer needs clearing between calls.
+ */
+#define KNN_NOALLOC_MAX_BYTES (64u * 1024u * 1024u)
+int knn_search_noalloc(const float* Q, int64_t n, const float* R, int64_t m, int32_t d, int32_t k,
+                       int32_t metric, float* dist, int32_t* idx, void* stream);
+
+/*
  * knn_search_mahalanobis -- brute force under a Mahalanobis distance, one of
  * the distances the problem definition of Section 2.1 names:
  *   d_M(q, r) = sqrt((q - r)^T Sigma^-1 (q - r)) = ||L^T (q - r)||,

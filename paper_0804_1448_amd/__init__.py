@@ -18,7 +18,7 @@ import torch
 from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
                    ServerStats, check, load)
 
-__all__ = ["search", "search_mahalanobis", "classify", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
+__all__ = ["search", "search_noalloc", "search_mahalanobis", "classify", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
            "timing"]
 
 KERNELS = ("centre", "prep_refs", "prep_queries", "fused_l2_f32", "fused_l2_bf16", "fused_l2_f16",
@@ -88,6 +88,23 @@ def search(Q: torch.Tensor, R: torch.Tensor, k: int, metric: str = "l2", out=Non
     check(lib.knn_search(ctypes.c_void_p(Q.data_ptr()), n, ctypes.c_void_p(R.data_ptr()), m, d, int(k),
                          METRICS[metric], ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
                          _stream_ptr(stream)))
+    return dist, idx
+
+
+def search_noalloc(Q: torch.Tensor, R: torch.Tensor, k: int, metric: str = "l2", out=None, stream=None):
+    """knn_search with the library's fixed device workspace (knn_search_noalloc):
+    the library allocates nothing; pass ``out=(dist, idx)`` to allocate nothing here either."""
+    lib = load()
+    Q = _points(Q, "Q")
+    R = _points(R, "R")
+    if Q.shape[1] != R.shape[1]:
+        raise ValueError("Q and R differ in dimension")
+    n, d = Q.shape
+    m = R.shape[0]
+    dist, idx = _outputs(n, k, Q.device, out)
+    check(lib.knn_search_noalloc(ctypes.c_void_p(Q.data_ptr()), n, ctypes.c_void_p(R.data_ptr()), m, d, int(k),
+                                 METRICS[metric], ctypes.c_void_p(dist.data_ptr()), ctypes.c_void_p(idx.data_ptr()),
+                                 _stream_ptr(stream)))
     return dist, idx
 
 

@@ -19,6 +19,8 @@ SIGNATURES = {
     "knn_last_error": (_c.c_char_p, []),
     "knn_search": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32,
                               _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    "knn_search_noalloc": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int32,
+                                      _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "knn_search_mahalanobis": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,
                                           _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "knn_classify": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_int64, _c.c_int32, _c.c_void_p,

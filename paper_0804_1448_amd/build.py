@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libknn.so")
-SOURCES = ["knn_kernels.hip", "knn_api.cpp", "knn_server.cpp", "knn_wide.hip", "knn_lane.hip", "knn_lane_l2.hip"] + [
+SOURCES = ["knn_kernels.hip", "knn_api.cpp", "knn_server.cpp", "knn_noalloc.hip", "knn_wide.hip", "knn_lane.hip", "knn_lane_l2.hip"] + [
     f"knn_fused_{unit}_{v}.hip" for unit in ("f32lo", "f32hi", "bf16", "f16", "l1", "linf") for v in ("s", "l")]
 
 # Packed float32 instructions are disabled on purpose: the compiler emits
