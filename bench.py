@@ -43,6 +43,10 @@ PEAK_BF16_MFMA_TFLOPS = 2516.6
 # 256 CUs x 64 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
+# rates measured on one MI355X by `bench.py --mode peaks` (profiles/peaks_mi355x.md)
+MEASURED_FP32_MFMA_TFLOPS = 155.3
+MEASURED_BF16_MFMA_TFLOPS = 2170.8
+MEASURED_VALU_TOPS = 41.78
 
 WORKLOAD_METRICS = {
     "gmm16384_d96": ["l2", "l1"],
@@ -60,12 +64,15 @@ def kernel_roofline(name: str, avg_s: float, pairs: float, d: float):
         flops = 2.0 * d * pairs  # cross term q.r: d multiply-adds per pair
         peak = PEAK_FP32_MFMA_TFLOPS if name.endswith("f32") else PEAK_BF16_MFMA_TFLOPS
         ach = flops / avg_s / 1e12
+        measured = MEASURED_FP32_MFMA_TFLOPS if name.endswith("f32") else MEASURED_BF16_MFMA_TFLOPS
         return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "measured_peak": measured, "frac_of_measured": ach / measured,
                 "traffic": None, "traffic_unit": "HBM bytes per launch", "kernel": name, "avg_ms": avg_s * 1e3,
                 "work_per_launch": flops}
     ops = 2.0 * d * pairs  # one subtract + one absolute accumulate (sum or max) per pair and dimension
     ach = ops / avg_s / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TFLOP/s", "frac": ach / PEAK_VALU_TOPS,
+            "measured_peak": MEASURED_VALU_TOPS, "frac_of_measured": ach / MEASURED_VALU_TOPS,
             "traffic": None, "traffic_unit": "HBM bytes per launch", "kernel": name, "avg_ms": avg_s * 1e3,
             "work_per_launch": ops}
 
@@ -797,13 +804,66 @@ def bench_copy(args):
                          "frac": gbs / PEAK_HBM_GBS, "traffic": None}}
 
 
+def bench_peaks(args):
+    """Measured issue rates of the instructions the roofline peaks assume:
+    the Manhattan kernel's vector subtract (DPP operand) + absolute add, the
+    BF16 32x32x16 and float32 32x32x2 matrix instructions; each with the
+    shader clock of the run (s_memtime against the 100 MHz s_memrealtime)."""
+    import ctypes
+
+    import torch
+
+    import paper_0804_1448_amd.build as B
+
+    lib = ctypes.CDLL(B.PEAKS_LIB)
+    lib.knn_peak_launch.restype = ctypes.c_int
+    lib.knn_peak_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    # (name, which, workgroups of 4 waves, iterations, work per wave and iteration, unit, datasheet peak)
+    cases = [("valu_sub_dpp_absadd", 0, cus * 8, 20000, 64 * 16, "T lane-ops/s", PEAK_VALU_TOPS),
+             ("mfma_bf16_32x32x16", 1, cus * 8, 10000, 8 * 32768, "TFLOP/s", PEAK_BF16_MFMA_TFLOPS),
+             ("mfma_f32_32x32x2", 2, cus * 8, 10000, 8 * 4096, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS)]
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, which, blocks, iters, per_wave, unit, peak in cases:
+        buf = torch.empty(blocks * 256, device="cuda")
+        clk = torch.zeros(4, dtype=torch.int64, device="cuda")
+        launch = lambda: lib.knn_peak_launch(which, blocks, iters, ctypes.c_void_p(buf.data_ptr()),
+                                             ctypes.c_void_p(clk.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+        for _ in range(args.warmup):
+            if launch() != 0:
+                raise RuntimeError(f"peak kernel {name} launch failed")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            launch()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sec = ev0.elapsed_time(ev1) / 1e3 / args.steps
+        c = clk.cpu().tolist()
+        ghz = (c[2] - c[0]) / ((c[3] - c[1]) / 100e6) / 1e9 if c[3] > c[1] else float("nan")
+        work = float(blocks) * 4 * iters * per_wave
+        rate = work / sec / 1e12
+        per_cu_clk = work / sec / (cus * ghz * 1e9)
+        out[name] = {"rate": rate, "unit": unit, "datasheet_peak": peak, "frac_of_datasheet": rate / peak,
+                     "clock_ghz": ghz, "per_cu_per_clock": per_cu_clk, "peak_at_2p4ghz": per_cu_clk * cus * 2.4e9 / 1e12,
+                     "ms": sec * 1e3}
+        log(f"[bench] {name}: {rate:.2f} {unit} ({rate / peak:.3f} of {peak:.1f}) at {ghz:.3f} GHz, "
+            f"{per_cu_clk:.1f} per CU per clock")
+    return {"metric": "measured peak issue rates", "value": out["mfma_bf16_32x32x16"]["rate"], "unit": "TFLOP/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16/f32", "data": "synthetic", "config": {"workload": "peaks", "cus": cus},
+            "peaks": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--mode", default="precision", choices=["pairs", "precision", "batched", "serve", "copy", "entropy",
-                                                      "mahalanobis", "classify", "table"])
+                                                      "mahalanobis", "classify", "table", "peaks"])
     ap.add_argument("--workload", default="gmm16384_d96", choices=sorted(WORKLOAD_METRICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the oracle sample")
@@ -827,7 +887,7 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path does not shard "
               "across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"pairs": (50, 5), "precision": (10, 2), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3), "table": (5, 1)}
+    defaults = {"pairs": (50, 5), "precision": (10, 2), "batched": (10, 2), "serve": (0, 0), "copy": (20, 3), "entropy": (20, 3), "mahalanobis": (20, 3), "classify": (20, 3), "table": (5, 1), "peaks": (5, 1)}
     if args.steps is None:
         args.steps = defaults[args.mode][0]
     if args.warmup is None:
@@ -842,7 +902,7 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     fn = {"pairs": bench_pairs, "precision": bench_precision, "batched": bench_batched, "serve": bench_serve,
           "copy": bench_copy, "entropy": bench_entropy, "mahalanobis": bench_mahalanobis,
-          "classify": bench_classify, "table": bench_table}
+          "classify": bench_classify, "table": bench_table, "peaks": bench_peaks}
     print(json.dumps(fn[args.mode](args)), flush=True)
 
 

@@ -68,7 +68,8 @@ enum knn_status {
   KNN_ERR_UNSUPPORTED = -2, /* valid request the library does not implement    */
   KNN_ERR_OOM = -3,         /* device or host memory exhausted                 */
   KNN_ERR_DEVICE = -4,      /* a HIP call failed                               */
-  KNN_ERR_BUSY = -5         /* serving back-pressure: retry later              */
+  KNN_ERR_BUSY = -5,        /* serving back-pressure: retry later              */
+  KNN_ERR_CANCELLED = -6    /* serving: the request was withdrawn              */
 };
 
 typedef struct knn_refs_s* knn_refs_t; /* opaque, owned by the library */
@@ -307,11 +308,20 @@ int knn_search_batched(const knn_problem_t* probs, int32_t count, int32_t precis
  *     memory budget.
  *   Scheduling: requests are admitted in arrival order.  The oldest waiting
  *     request heads the next batch, which also takes later waiting requests
- *     of the same set and k, up to cfg->max_batch_queries queries, as long
- *     as the batch's memory fits in the arena; a batch launches as soon as a
- *     stream is free, so batches of different sets (or successive batches of
- *     one set) run on the device at the same time.  A request's result does
- *     not depend on the requests it is batched with.
+ *     of the same set (any k), up to cfg->max_batch_queries queries, as long
+ *     as the batch's memory fits in the arena; the batch keeps the largest
+ *     k' of its requests and finalizes each request with its own k.  A head
+ *     that waits for memory lets later requests that fit head batches for
+ *     at most 50 ms.  A batch launches as soon as a stream is free, so
+ *     batches of different sets (or successive batches of one set) run on
+ *     the device at the same time.  A request's result does not depend on
+ *     the requests it is batched with.
+ *   knn_server_cancel(srv, ticket): withdraws a request that is still
+ *     waiting: it completes at once, its host arrays untouched, and poll /
+ *     wait then report KNN_ERR_CANCELLED.  A request already on the device
+ *     (or complete) cannot be withdrawn: KNN_ERR_BUSY, and it completes
+ *     normally.  A client-side timeout is poll until the deadline, then
+ *     cancel.
  *   knn_server_poll / knn_server_wait: completion and latency (microseconds
  *     from submit to results in host memory).  A ticket retires once poll
  *     has reported it done or wait has returned; a request that failed on
@@ -351,6 +361,7 @@ typedef struct {
   int32_t peak_batches_in_flight;
   int64_t peak_mem_in_flight;  /* arena bytes */
   int64_t mem_budget;
+  int64_t cancelled;           /* requests withdrawn by knn_server_cancel */
 } knn_server_stats_t;
 
 int knn_server_create(const knn_refs_t* sets, int32_t nsets, const knn_server_config_t* cfg,
@@ -359,6 +370,7 @@ int knn_server_submit(knn_server_t srv, int32_t set, const float* Q_host, int64_
                       float* dist_host, int32_t* idx_host, uint64_t* ticket);
 int knn_server_poll(knn_server_t srv, uint64_t ticket, int32_t* done, double* latency_us);
 int knn_server_wait(knn_server_t srv, uint64_t ticket, double* latency_us);
+int knn_server_cancel(knn_server_t srv, uint64_t ticket);
 int knn_server_stats(knn_server_t srv, knn_server_stats_t* out);
 int knn_server_destroy(knn_server_t srv);
 

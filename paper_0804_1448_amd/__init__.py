@@ -335,6 +335,15 @@ class Server:
         _, dist, idx = self._live.pop(ticket)
         return dist, idx, lat.value
 
+    def cancel(self, ticket: int) -> bool:
+        """Withdraw a request that is still waiting (True); False when it is
+        already on the device or complete (it then completes normally)."""
+        st = load().knn_server_cancel(self._h, ctypes.c_uint64(ticket))
+        if st == KNN_ERR_BUSY:
+            return False
+        check(st)
+        return True
+
     def wait(self, ticket: int):
         lat = ctypes.c_double()
         st = load().knn_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(lat))

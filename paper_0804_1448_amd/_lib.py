@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libknn.so")
 
 KNN_OK = 0
-STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BUSY"}
+STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BUSY", -6: "CANCELLED"}
 METRICS = {"l2": 0, "l1": 1, "linf": 2}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 
@@ -46,6 +46,7 @@ SIGNATURES = {
                                      _c.c_void_p, _c.POINTER(_c.c_uint64)]),
     "knn_server_poll": (_c.c_int, [_c.c_void_p, _c.c_uint64, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double)]),
     "knn_server_wait": (_c.c_int, [_c.c_void_p, _c.c_uint64, _c.POINTER(_c.c_double)]),
+    "knn_server_cancel": (_c.c_int, [_c.c_void_p, _c.c_uint64]),
     "knn_server_stats": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "knn_server_destroy": (_c.c_int, [_c.c_void_p]),
 }
@@ -72,10 +73,11 @@ class ServerStats(_c.Structure):
 
     _fields_ = [("submitted", _c.c_int64), ("completed", _c.c_int64), ("rejected_busy", _c.c_int64),
                 ("batches", _c.c_int64), ("queries", _c.c_int64), ("peak_batches_in_flight", _c.c_int32),
-                ("peak_mem_in_flight", _c.c_int64), ("mem_budget", _c.c_int64)]
+                ("peak_mem_in_flight", _c.c_int64), ("mem_budget", _c.c_int64), ("cancelled", _c.c_int64)]
 
 
 KNN_ERR_BUSY = -5
+KNN_ERR_CANCELLED = -6
 KNN_SERVER_DRY_RUN = 1
 
 

@@ -9,6 +9,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libknn.so")
+# measurement only (the benchmark's peak-rate micro-kernels), not the k-NN ABI
+PEAKS_SRC = "knn_peaks.hip"
+PEAKS_LIB = os.path.join(PKG, "libknn_peaks.so")
 SOURCES = ["knn_kernels.hip", "knn_api.cpp", "knn_server.cpp", "knn_noalloc.hip", "knn_wide.hip", "knn_lane.hip", "knn_lane_l2.hip"] + [
     f"knn_fused_{unit}_{v}.hip" for unit in ("f32lo", "f32hi", "bf16", "f16", "l1", "linf") for v in ("s", "l")]
 
@@ -34,7 +37,8 @@ def _compile(src: str, obj: str):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source (in parallel) and link ``libknn.so``; always recompiles."""
+    """Compile every source (in parallel) and link ``libknn.so`` and
+    ``libknn_peaks.so``; always recompiles."""
     import tempfile
 
     with tempfile.TemporaryDirectory(prefix="knn_build_") as tmpd:
@@ -42,6 +46,8 @@ def build(verbose: bool = False) -> str:
         for s in SOURCES:
             obj = os.path.join(tmpd, s + ".o")
             jobs.append((obj, *_compile(os.path.join(CSRC, s), obj)))
+        pobj = os.path.join(tmpd, PEAKS_SRC + ".o")
+        pproc, pcmd = _compile(os.path.join(CSRC, PEAKS_SRC), pobj)
         errs = []
         for obj, proc, cmd in jobs:
             out, err = proc.communicate()
@@ -50,6 +56,9 @@ def build(verbose: bool = False) -> str:
                 errs.append(" ".join(cmd) + "\n" + "\n".join(lines))
             elif verbose and lines:
                 print("\n".join(lines), file=sys.stderr)
+        _, perr = pproc.communicate()
+        if pproc.returncode != 0:
+            errs.append(" ".join(pcmd) + "\n" + perr)
         if errs:
             raise RuntimeError("hipcc failed:\n" + "\n\n".join(errs))
         tmp = LIB + ".tmp"
@@ -60,6 +69,12 @@ def build(verbose: bool = False) -> str:
         if res.returncode != 0:
             raise RuntimeError("link failed:\n" + res.stderr)
         os.replace(tmp, LIB)
+        ptmp = PEAKS_LIB + ".tmp"
+        res = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", pobj, "-o", ptmp],
+                             capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + res.stderr)
+        os.replace(ptmp, PEAKS_LIB)
     return LIB
 
 

@@ -547,6 +547,7 @@ int knn_server_poll(knn_server_t srv, uint64_t ticket, int32_t* done, double* la
     if (latency_us) *latency_us = std::chrono::duration<double, std::micro>(r.t_done - r.t_submit).count();
     const int status = r.status;
     srv->requests.erase(it);
+    if (status == KNN_ERR_CANCELLED) return fail(status, "request %llu was cancelled", (unsigned long long)ticket);
     if (status != KNN_OK) return fail(status, "request %llu failed on the device", (unsigned long long)ticket);
   }
   return KNN_OK;
@@ -563,6 +564,27 @@ int knn_server_wait(knn_server_t srv, uint64_t ticket, double* latency_us) {
   }
   int32_t done = 0;
   return knn_server_poll(srv, ticket, &done, latency_us);
+}
+
+int knn_server_cancel(knn_server_t srv, uint64_t ticket) {
+  if (!valid_server(srv)) return fail(KNN_ERR_INVALID, "not a live server handle");
+  {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->requests.find(ticket);
+    if (it == srv->requests.end()) return fail(KNN_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    Request& r = *it->second;
+    if (r.state != 0)
+      return fail(KNN_ERR_BUSY, "request %llu is already %s", (unsigned long long)ticket,
+                  r.state == 1 ? "on the device" : "complete");
+    srv->waiting.erase(std::find(srv->waiting.begin(), srv->waiting.end(), &r));
+    r.state = 2;
+    r.status = KNN_ERR_CANCELLED;
+    r.t_done = Clock::now();
+    ++srv->stats.cancelled;
+    ++srv->stats.completed;
+  }
+  srv->cv_done.notify_all();
+  return KNN_OK;
 }
 
 int knn_server_stats(knn_server_t srv, knn_server_stats_t* out) {

@@ -218,3 +218,32 @@ def test_create_validation(K):
     assert lib.knn_server_submit(None, 0, None, 1, 1, None, None, None) == -1
     assert lib.knn_server_destroy(None) == -1
     assert not h.value
+
+
+def test_cancel_withdraws_waiting_requests_only(K):
+    """A waiting request can be withdrawn: it completes at once as
+    CANCELLED, its host arrays untouched, and never reaches a batch.  A
+    request on the device (or complete) cannot: cancel says so and it
+    completes normally."""
+    with K.Server.dry(1, m=500, d=D, us_per_query=2000.0, max_batches=1, max_batch_queries=8) as srv:
+        first = srv.submit(0, q(8), 3)            # fills the only stream for 16 ms
+        time.sleep(0.005)
+        later = [srv.submit(0, q(8, i), 3) for i in range(1, 4)]  # each a batch of its own, waiting
+        _, dist_w, idx_w = srv._live[later[1]]
+        dist_w[:] = -5.0
+        idx_w[:] = -9
+        assert srv.cancel(later[1]) is True
+        with pytest.raises(K.KnnError) as ei:
+            srv.wait(later[1])
+        assert ei.value.status == -6
+        assert np.all(dist_w == -5.0) and np.all(idx_w == -9), "a cancelled request's arrays were written"
+        assert srv.cancel(first) is False         # on the device
+        d0, i0, _ = srv.wait(first)
+        assert np.all(d0 == 0)
+        seqs = [srv.wait(t)[1][0, 0] for t in (later[0], later[2])]
+        assert seqs == [1, 2], "the cancelled request took a launch"
+        with pytest.raises(K.KnnError):
+            srv.cancel(first)                     # retired ticket
+        st = srv.stats()
+        assert st["cancelled"] == 1 and st["batches"] == 3
+        assert st["submitted"] == st["completed"] == 4
