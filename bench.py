@@ -547,8 +547,8 @@ def bench_serve(args):
     mean_pairs = float(np.mean([n * spec["sets"][s] for _, s, _, n, _ in trace]))
     out = {}
     for tag, sets, prec in (("fp16", sets16, "fp16"), ("fp32", sets32, "fp32")):
-        srv = K.Server(sets, mem_budget=args.serve_mem << 30, max_batches=4, max_queue=4096,
-                       max_batch_queries=8192, precision=prec, s_extra=args.serve_extra)
+        srv = K.Server(sets, mem_budget=args.serve_mem << 30, max_batches=args.serve_streams, max_queue=4096,
+                       max_batch_queries=8192, precision=prec, s_extra=args.serve_extra, one_set=args.serve_one_set)
         # capacity: closed loop over the first requests, all submitted at once
         cal = trace[: min(len(trace), 200)]
         _, wall_c, cnt_c, _ = run_trace(K, srv, pools, cal, rate=1e9)
@@ -566,6 +566,10 @@ def bench_serve(args):
                 "busy_retries": rej}
             log(f"[bench] serve {tag} load {load:g}: {res[f'load{load:g}']}")
         res["stats"] = srv.stats()
+        res["requests_per_launch"] = res["stats"]["submitted"] / max(1, res["stats"]["batches"])
+        res["queries_per_launch"] = res["stats"]["queries"] / max(1, res["stats"]["batches"])
+        log(f"[bench] serve {tag}: {res['requests_per_launch']:.2f} requests and {res['queries_per_launch']:.0f} "
+            f"queries per launch")
         srv.close()
         out[tag] = res
     # parity of the serving path on a few requests against the oracle
@@ -586,6 +590,7 @@ def bench_serve(args):
                    "request_queries": list(spec["n"]), "sizes": args.sizes, "k": list(spec["k"]),
                    "arrivals": "Poisson",
                    "mem_budget_gib": args.serve_mem, "mean_pairs_per_request": mean_pairs,
+                   "streams": args.serve_streams, "one_set_batches": args.serve_one_set,
                    "s_extra": args.serve_extra},
         "serve": out,
     }
@@ -851,6 +856,31 @@ def bench_peaks(args):
                      "ms": sec * 1e3}
         log(f"[bench] {name}: {rate:.2f} {unit} ({rate / peak:.3f} of {peak:.1f}) at {ghz:.3f} GHz, "
             f"{per_cu_clk:.1f} per CU per clock")
+    # BF16 matrix rate by independent accumulator chains per wave and waves per SIMD
+    lib.knn_peak_launch_chains.restype = ctypes.c_int
+    lib.knn_peak_launch_chains.argtypes = lib.knn_peak_launch.argtypes
+    chains = {}
+    for ch in (1, 2, 4, 8):
+        for wps in (1, 2, 4, 8):
+            blocks, iters = cus * wps, 8192 // ch
+            buf = torch.empty(blocks * 256, device="cuda")
+            clk = torch.zeros(4, dtype=torch.int64, device="cuda")
+            launch = lambda: lib.knn_peak_launch_chains(ch, blocks, iters, ctypes.c_void_p(buf.data_ptr()),
+                                                        ctypes.c_void_p(clk.data_ptr()),
+                                                        ctypes.c_void_p(stream.cuda_stream))
+            if launch() != 0:
+                raise RuntimeError("peak chains kernel launch failed")
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for _ in range(3):
+                launch()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            sec = ev0.elapsed_time(ev1) / 3e3
+            chains[f"chains{ch}_waves{wps}"] = float(blocks) * 4 * iters * ch * 32768 / sec / 1e12
+        log(f"[bench] bf16 MFMA, {ch} chains per wave, 1/2/4/8 waves per SIMD: "
+            + " / ".join(f"{chains[f'chains{ch}_waves{w}']:.0f}" for w in (1, 2, 4, 8)) + " TFLOP/s")
+    out["mfma_bf16_by_chains_and_waves_tflops"] = chains
     return {"metric": "measured peak issue rates", "value": out["mfma_bf16_32x32x16"]["rate"], "unit": "TFLOP/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "bf16/f32", "data": "synthetic", "config": {"workload": "peaks", "cus": cus},
@@ -878,6 +908,9 @@ def main():
                     help="serve mode: request size distribution")
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 0.8], help="serve mode: fractions of capacity")
     ap.add_argument("--serve-mem", type=int, default=8, help="serve mode: request memory budget, GiB")
+    ap.add_argument("--serve-streams", type=int, default=2, help="serve mode: batches in flight (one stream each)")
+    ap.add_argument("--serve-one-set", action="store_true",
+                    help="serve mode: batch requests of one set only (16-bit sets otherwise share launches)")
     ap.add_argument("--serve-extra", type=int, default=14,
                     help="serve mode: extra candidates re-ranked per query (k + extra <= 64 keeps every request "
                          "on the 32x32-tile kernel for k <= 50)")

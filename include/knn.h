@@ -307,15 +307,19 @@ int knn_search_batched(const knn_problem_t* probs, int32_t count, int32_t precis
  *     later) and KNN_ERR_UNSUPPORTED when the request alone exceeds the
  *     memory budget.
  *   Scheduling: requests are admitted in arrival order.  The oldest waiting
- *     request heads the next batch, which also takes later waiting requests
- *     of the same set (any k), up to cfg->max_batch_queries queries, as long
- *     as the batch's memory fits in the arena; the batch keeps the largest
- *     k' of its requests and finalizes each request with its own k.  A head
- *     that waits for memory lets later requests that fit head batches for
- *     at most 50 ms.  A batch launches as soon as a stream is free, so
- *     batches of different sets (or successive batches of one set) run on
- *     the device at the same time.  A request's result does not depend on
- *     the requests it is batched with.
+ *     request heads the next batch, which also takes later waiting requests,
+ *     up to cfg->max_batch_queries queries, as long as the batch's memory
+ *     fits in the arena.  With 16-bit sets (cfg->precision KNN_BF16 or
+ *     KNN_FP16) a batch takes the waiting requests of every set whose
+ *     k + s_extra <= 128 and runs them in one launch of the 32x32-tile
+ *     kernel, each request against its own set with its own k; otherwise
+ *     (float32 sets, larger k, or the KNN_SERVER_ONE_SET flag) a batch takes
+ *     requests of the head's set only, searched with the largest k' of the
+ *     batch and finalized per request with its own k.  A head that waits for
+ *     memory lets later requests that fit head batches for at most 50 ms.  A
+ *     batch launches as soon as a stream is free, so several batches can run
+ *     on the device at the same time.  A request's result does not depend
+ *     on the requests it is batched with.
  *   knn_server_cancel(srv, ticket): withdraws a request that is still
  *     waiting: it completes at once, its host arrays untouched, and poll /
  *     wait then report KNN_ERR_CANCELLED.  A request already on the device
@@ -337,7 +341,7 @@ int knn_search_batched(const knn_problem_t* probs, int32_t count, int32_t precis
  */
 typedef struct knn_server_s* knn_server_t;
 
-enum knn_server_flags { KNN_SERVER_DRY_RUN = 1 };
+enum knn_server_flags { KNN_SERVER_DRY_RUN = 1, KNN_SERVER_ONE_SET = 2 };
 
 typedef struct {
   int64_t mem_budget;        /* device bytes for requests in flight */

@@ -15,7 +15,7 @@ import ctypes
 
 import torch
 
-from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
+from ._lib import (KNN_ERR_BUSY, KNN_SERVER_DRY_RUN, KNN_SERVER_ONE_SET, METRICS, PRECISIONS, KnnError, Problem, ServerConfig,
                    ServerStats, check, load)
 
 __all__ = ["search", "search_noalloc", "search_mahalanobis", "classify", "entropy", "Refs", "Batch", "search_batched", "Server", "KnnError", "METRICS", "PRECISIONS", "load",
@@ -274,7 +274,7 @@ class Server:
     """
 
     def __init__(self, sets, mem_budget: int, max_batches: int = 4, max_queue: int = 1024,
-                 max_batch_queries: int = 4096, precision: str = "fp32", s_extra: int = -1):
+                 max_batch_queries: int = 4096, precision: str = "fp32", s_extra: int = -1, one_set: bool = False):
         import numpy as np
 
         self._np = np
@@ -284,7 +284,7 @@ class Server:
             raise ValueError("at least one reference set is required")
         self.d = self._sets[0].d
         cfg = ServerConfig(int(mem_budget), int(max_batches), int(max_queue), int(max_batch_queries),
-                           PRECISIONS[precision], int(s_extra), 0, 0, 0, 0.0)
+                           PRECISIONS[precision], int(s_extra), KNN_SERVER_ONE_SET if one_set else 0, 0, 0, 0.0)
         arr = (ctypes.c_void_p * len(self._sets))(*[r.handle.value for r in self._sets])
         h = ctypes.c_void_p()
         check(lib.knn_server_create(arr, len(self._sets), ctypes.byref(cfg), ctypes.byref(h)))
@@ -301,7 +301,8 @@ class Server:
         lib = load()
         cfg = ServerConfig(int(kw.get("mem_budget", 1 << 30)), int(kw.get("max_batches", 4)),
                            int(kw.get("max_queue", 1024)), int(kw.get("max_batch_queries", 4096)),
-                           PRECISIONS[kw.get("precision", "fp32")], int(kw.get("s_extra", -1)), KNN_SERVER_DRY_RUN,
+                           PRECISIONS[kw.get("precision", "fp32")], int(kw.get("s_extra", -1)),
+                           KNN_SERVER_DRY_RUN | (KNN_SERVER_ONE_SET if kw.get("one_set") else 0),
                            int(m), int(d), float(us_per_query))
         h = ctypes.c_void_p()
         check(lib.knn_server_create(None, int(nsets), ctypes.byref(cfg), ctypes.byref(h)))

@@ -5,7 +5,9 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libknn.so")
+# KNN_LIB_PATH selects another build of the same library (the host-sanitizer
+# build the CPU tests load); the default is the in-tree libknn.so
+LIB_PATH = os.environ.get("KNN_LIB_PATH") or os.path.join(PKG, "libknn.so")
 
 KNN_OK = 0
 STATUS = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "OOM", -4: "DEVICE", -5: "BUSY", -6: "CANCELLED"}
@@ -79,6 +81,7 @@ class ServerStats(_c.Structure):
 KNN_ERR_BUSY = -5
 KNN_ERR_CANCELLED = -6
 KNN_SERVER_DRY_RUN = 1
+KNN_SERVER_ONE_SET = 2
 
 
 class KnnError(RuntimeError):

@@ -31,8 +31,16 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str, obj: str):
-    cmd = [hipcc(), *HIPCC_FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build (host code
+# only: the device code of this build is the ordinary one), for the CPU tests
+# of the host logic; loaded with the toolchain's ASan runtime preloaded.
+ASAN_LIB = os.path.join(ROOT, "_build", "libknn_asan.so")
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def _compile(src: str, obj: str, extra=()):
+    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True), cmd
 
 
@@ -76,6 +84,46 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError("link failed:\n" + res.stderr)
         os.replace(ptmp, PEAKS_LIB)
     return LIB
+
+
+def asan_runtime() -> str:
+    """The toolchain's shared ASan runtime (to preload into the host process)."""
+    import glob
+
+    found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found under /opt/rocm/llvm")
+    return found[-1]
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """Compile every source with host AddressSanitizer and UBSan into
+    _build/libknn_asan.so; always recompiles."""
+    import tempfile
+
+    os.makedirs(os.path.dirname(ASAN_LIB), exist_ok=True)
+    with tempfile.TemporaryDirectory(prefix="knn_asan_") as tmpd:
+        jobs = []
+        for s in SOURCES:
+            obj = os.path.join(tmpd, s + ".o")
+            jobs.append((obj, *_compile(os.path.join(CSRC, s), obj, SANITIZE_FLAGS)))
+        errs = []
+        for obj, proc, cmd in jobs:
+            _, err = proc.communicate()
+            if proc.returncode != 0:
+                errs.append(" ".join(cmd) + "\n" + err)
+        if errs:
+            raise RuntimeError("hipcc failed:\n" + "\n\n".join(errs))
+        tmp = ASAN_LIB + ".tmp"
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-Xarch_host", "-fsanitize=address",
+                "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", *[o for o, _, _ in jobs], "-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        res = subprocess.run(link, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + res.stderr)
+        os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
 
 
 if __name__ == "__main__":

@@ -589,6 +589,247 @@ size_t sub_tables_bytes(int nsubs, int64_t n) {
   return (size_t)round_up(round_up(nsubs * (int64_t)sizeof(FinalInst), 16) + items * (int64_t)sizeof(FinalItem), 256);
 }
 
+// ------------------------------------------------- multi-set search
+// Several requests (each: some query rows against one resident 16-bit set,
+// with its own k) in one launch of the 32x32 register-list kernel.  Layout
+// of the workspace: per request its prepared queries and slice lists (and
+// merged lists when it has more slices than the finalize takes), then the
+// tables -- query preparation jobs, fused instances, fused items, finalize
+// instances, finalize items, the item counter -- which the host writes to
+// `tables_host` and one copy moves to the device.
+
+int tile_kind(int metric, int precision);
+
+bool multi_supported(const knn_refs_s* r, int precision, int kprime) {
+  if (!(precision == KNN_BF16 || precision == KNN_FP16) || r->storage != precision) return false;
+  const int kind = tile_kind(KNN_L2, precision);
+  return kprime <= kWideMaxKc && padded_dim(kind, r->d) <= kWideMaxDp;
+}
+
+namespace {
+
+struct MultiPlan {
+  struct Req {
+    int P = 1, G = 1, P2 = 1;
+    int64_t slice_len = 0;
+    size_t q_off = 0, part_off = 0, part2_off = 0;
+  };
+  std::vector<Req> req;
+  int dp = 0, kind = 0;
+  int64_t nitems = 0, nfitems = 0;
+  size_t tables_off = 0, jobs_off = 0, insts_off = 0, items_off = 0, finsts_off = 0, fitems_off = 0, counter_off = 0;
+  size_t total = 0, tables_bytes = 0;
+};
+
+int multi_plan(const MultiReq* reqs, int nreq, int precision, MultiPlan* out) {
+  MultiPlan& mp = *out;
+  mp = MultiPlan{};
+  mp.kind = tile_kind(KNN_L2, precision);
+  mp.req.resize(nreq);
+  // one slice length for the launch: about four items per CU over all the
+  // requests' query blocks, at least 16 steps
+  int64_t work = 0;
+  for (int i = 0; i < nreq; ++i) {
+    const MultiReq& r = reqs[i];
+    if (!valid_refs(r.refs) || !multi_supported(r.refs, precision, r.kprime) || r.n < 1 || r.k < 1 ||
+        r.k > r.kprime || r.kprime > r.refs->m)
+      return fail(KNN_ERR_INVALID, "request %d of the multi-set search is not supported", i);
+    if (i > 0 && r.refs->d != reqs[0].refs->d) return fail(KNN_ERR_INVALID, "requests differ in dimension");
+    work += ceil_div(r.n, (int64_t)kWideQueries) * r.refs->m;
+  }
+  mp.dp = padded_dim(mp.kind, reqs[0].refs->d);
+  const int64_t target = std::max<int64_t>(16 * kStepRefs, round_up(ceil_div(work, 4 * (int64_t)device_cu_count()),
+                                                                     kStepRefs));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 256);
+    return at;
+  };
+  for (int i = 0; i < nreq; ++i) {
+    const MultiReq& r = reqs[i];
+    MultiPlan::Req& q = mp.req[i];
+    const int64_t m = r.refs->m;
+    // slices: up to kMaxSlices, merged in groups first when more than the
+    // finalize takes (k' <= 64 only)
+    const int64_t p2max = std::min<int64_t>(64, kFinalMaxKeys / r.kprime);
+    const int64_t pcap = r.kprime <= 64 ? kMaxSlices : p2max;
+    const int64_t P = std::max<int64_t>(1, std::min<int64_t>({pcap, ceil_div(m, target), m / (4 * (int64_t)r.kprime) + 1}));
+    q.slice_len = round_up(ceil_div(m, P), kStepRefs);
+    q.P = (int)ceil_div(m, q.slice_len);
+    q.G = q.P <= p2max ? 1 : (int)ceil_div(q.P, p2max);
+    q.P2 = (int)ceil_div(q.P, q.G);
+    q.q_off = take((size_t)r.n * mp.dp * 2);
+    q.part_off = take((size_t)r.n * q.P * r.kprime * 8);
+    if (q.G > 1) q.part2_off = take((size_t)r.n * q.P2 * r.kprime * 8);
+    mp.nitems += ceil_div(r.n, (int64_t)kWideQueries) * q.P;
+    mp.nfitems += ceil_div(r.n, (int64_t)kFinalWaves);
+  }
+  mp.tables_off = off;
+  size_t toff = 0;
+  auto ttake = [&](size_t bytes) {
+    const size_t at = toff;
+    toff += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 16);
+    return at;
+  };
+  mp.jobs_off = ttake(nreq * sizeof(PrepJob));
+  mp.insts_off = ttake(nreq * sizeof(FusedInst));
+  mp.items_off = ttake((size_t)mp.nitems * sizeof(FusedItem));
+  mp.finsts_off = ttake(nreq * sizeof(FinalInst));
+  mp.fitems_off = ttake((size_t)mp.nfitems * sizeof(FinalItem));
+  mp.counter_off = ttake(sizeof(int));
+  mp.tables_bytes = (size_t)round_up((int64_t)toff, 256);
+  mp.total = mp.tables_off + mp.tables_bytes;
+  return KNN_OK;
+}
+
+}  // namespace
+
+int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, void* ws_in, size_t ws_size,
+                 size_t* need, void* tables_host, size_t* tables_need, hipStream_t stream) {
+  if (nreq < 1) return fail(KNN_ERR_INVALID, "no request");
+  MultiPlan mp;
+  int st = multi_plan(reqs, nreq, precision, &mp);
+  if (st != KNN_OK) return st;
+  if (need) *need = mp.total;
+  if (tables_need) *tables_need = mp.tables_bytes;
+  if (!ws_in) return KNN_OK;
+  if (ws_size < mp.total) return fail(KNN_ERR_INVALID, "workspace of %zu bytes is smaller than the %zu needed",
+                                      ws_size, mp.total);
+  if (!tables_host) return fail(KNN_ERR_INVALID, "no host staging for the tables");
+  unsigned char* w = (unsigned char*)ws_in;
+  unsigned char* tdev = w + mp.tables_off;
+  unsigned char* th = (unsigned char*)tables_host;
+  PrepJob* jobs = (PrepJob*)(th + mp.jobs_off);
+  FusedInst* insts = (FusedInst*)(th + mp.insts_off);
+  FusedItem* items = (FusedItem*)(th + mp.items_off);
+  FinalInst* finsts = (FinalInst*)(th + mp.finsts_off);
+  FinalItem* fitems = (FinalItem*)(th + mp.fitems_off);
+  const int elem = elem_of_kind(mp.kind);
+  int64_t prep_rows = 0;
+  int kc_max = 0, keys_max = 0, p_max = 1, kprime_max = 0;
+  // items, longest first: full query blocks of long slices before the rest
+  struct Cost {
+    int64_t cost;
+    FusedItem it;
+  };
+  std::vector<Cost> all;
+  all.reserve((size_t)mp.nitems);
+  int64_t nf = 0;
+  for (int i = 0; i < nreq; ++i) {
+    const MultiReq& r = reqs[i];
+    const knn_refs_s* R = r.refs;
+    const MultiPlan::Req& q = mp.req[i];
+    PrepJob& jb = jobs[i];
+    jb = PrepJob{};
+    jb.src = Q + r.row0 * (int64_t)R->d;
+    jb.dst = w + q.q_off;
+    jb.centre = R->centre;
+    jb.rhalf = nullptr;
+    jb.rows = r.n;
+    jb.row0 = prep_rows;
+    jb.d = R->d;
+    jb.lds = R->d;
+    jb.ldd = mp.dp;
+    jb.elem = elem;
+    prep_rows += r.n;
+    FusedInst& fi = insts[i];
+    fi = FusedInst{};
+    fi.Q = w + q.q_off;
+    fi.R = R->rows;
+    fi.rhalf = R->rhalf;
+    fi.part = (uint64_t*)(w + q.part_off);
+    fi.n = r.n;
+    fi.m = R->m;
+    fi.slice_len = q.slice_len;
+    fi.ldq = mp.dp;
+    fi.ldr = R->dp;
+    fi.dp = mp.dp;
+    fi.nchunk = 1;
+    fi.P = q.P;
+    fi.kc = r.kprime;
+    const int64_t qb = ceil_div(r.n, (int64_t)kWideQueries);
+    for (int64_t b = 0; b < qb; ++b)
+      for (int sl = 0; sl < q.P; ++sl) {
+        const int64_t refs = std::min<int64_t>(q.slice_len, R->m - sl * q.slice_len);
+        all.push_back({refs * (mp.dp + 64), FusedItem{i, (int)b, sl, 0}});
+      }
+    FinalInst& f = finsts[i];
+    f = FinalInst{};
+    f.part = (const uint64_t*)(w + (q.G > 1 ? q.part2_off : q.part_off));
+    f.Q = Q + r.row0 * (int64_t)R->d;
+    f.ldq = R->d;
+    if (R->master) {
+      f.Rm = R->master;
+      f.rm_type = ELEM_F32;
+      f.ldr = R->dp32;
+    } else {
+      f.Rm = R->rows;
+      f.rm_type = elem;
+      f.ldr = R->dp;
+    }
+    f.dist = r.dist;
+    f.idx = r.idx;
+    f.n = r.n;
+    f.m = R->m;
+    f.d = R->d;
+    f.P = q.P2;
+    f.kc = r.kprime;
+    f.kprime = r.kprime;
+    f.k = r.k;
+    f.metric = KNN_L2;
+    for (int64_t q0 = 0; q0 < r.n; q0 += kFinalWaves) fitems[nf++] = FinalItem{i, (int)q0};
+    kc_max = std::max(kc_max, r.kprime);
+    keys_max = std::max(keys_max, q.P2 * r.kprime);
+    p_max = std::max(p_max, q.P2);
+    kprime_max = std::max(kprime_max, r.kprime);
+  }
+  std::stable_sort(all.begin(), all.end(), [](const Cost& x, const Cost& y) { return x.cost > y.cost; });
+  for (size_t j = 0; j < all.size(); ++j) items[j] = all[j].it;
+  *(int*)(th + mp.counter_off) = 0;
+  HIP_TRY(hipMemcpyAsync(tdev, th, mp.tables_bytes, hipMemcpyHostToDevice, stream), "multi-set tables copy");
+  int* counter = (int*)(tdev + mp.counter_off);
+  {
+    TimedLaunch tl("prep_queries", stream);
+    HIP_TRY(launch_prep_batched((const PrepJob*)(tdev + mp.jobs_off), nreq, prep_rows, stream, counter),
+            "multi-set query preparation launch");
+  }
+  FusedParams fp{};
+  fp.insts = (const FusedInst*)(tdev + mp.insts_off);
+  fp.items = (const FusedItem*)(tdev + mp.items_off);
+  fp.nitems = (int)mp.nitems;
+  fp.wide = 1;
+  fp.ng = mp.dp / 16;
+  fp.cb = 32;
+  fp.waves = 8;
+  fp.kc_max = kc_max;
+  fp.counter = counter;
+  {
+    TimedLaunch tl(fused_name(mp.kind), stream);
+    HIP_TRY(launch_fused(mp.kind, fp, stream), "multi-set fused launch");
+  }
+  for (int i = 0; i < nreq; ++i) {
+    const MultiPlan::Req& q = mp.req[i];
+    if (q.G <= 1) continue;
+    TimedLaunch tl("merge", stream);
+    HIP_TRY(launch_merge_lists((const uint64_t*)(w + q.part_off), (uint64_t*)(w + q.part2_off), reqs[i].n, q.P,
+                               reqs[i].kprime, q.G, q.P2, stream),
+            "slice-list merge launch");
+  }
+  FinalParams fin{};
+  fin.insts = (const FinalInst*)(tdev + mp.finsts_off);
+  fin.items = (const FinalItem*)(tdev + mp.fitems_off);
+  fin.nitems = (int)mp.nfitems;
+  fin.keys_max = keys_max;
+  fin.p_max = p_max;
+  fin.kprime_max = kprime_max;
+  {
+    TimedLaunch tl("finalize", stream);
+    HIP_TRY(launch_finalize(fin, stream), "multi-set finalize launch");
+  }
+  return KNN_OK;
+}
+
 // Run one search in the library's per-stream workspace.
 int run_search(const SearchArgs& a) {
   size_t need = 0;

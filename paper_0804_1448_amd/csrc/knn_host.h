@@ -129,4 +129,36 @@ extern thread_local bool g_tm_suppress;
 // needed size is stored in *need.
 int run_search_ws(const SearchArgs& a, void* ws, size_t ws_size, size_t* need);
 
+// One request of a multi-set search: query rows [row0, row0 + n) of the
+// concatenated float32 queries against resident set `refs`, with its own k
+// and k' (k <= k' <= m) and device outputs dist / idx [n][k].
+struct MultiReq {
+  knn_refs_s* refs;
+  int64_t row0;
+  int64_t n;
+  int k;
+  int kprime;
+  float* dist;
+  int32_t* idx;
+};
+
+// Whether a request of k' candidates against `refs` can join a multi-set
+// search in `precision` (16-bit sets stored in that precision, d <= 128,
+// k' <= 128).
+bool multi_supported(const knn_refs_s* refs, int precision, int kprime);
+
+// Euclidean searches of several requests against several resident 16-bit
+// sets of one dimension in one launch of the 32x32 register-list kernel:
+// one query preparation (which also zeroes the item counter), one fused
+// launch over (request, query block, slice) items taken longest first, the
+// slice-list merges of requests with many slices, one finalize with each
+// request's own k.  Q: the requests' float32 queries concatenated [N][d] on
+// the device.  The tables are built in `tables_host` (pinned host memory of
+// *tables_need bytes, valid until the search has run) and copied to the
+// workspace on `stream`.  With ws == nullptr only *need (workspace bytes)
+// and *tables_need are stored.  A request's result does not depend on the
+// other requests of the launch.
+int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, void* ws, size_t ws_size,
+                 size_t* need, void* tables_host, size_t* tables_need, hipStream_t stream);
+
 }  // namespace knn::host

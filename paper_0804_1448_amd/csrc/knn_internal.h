@@ -169,7 +169,7 @@ constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice wo
 // float32 lane kernel (measured: the lane kernel wins at slices of 16384 and
 // 19200, the 32x32 kernel at 2^20)
 constexpr int64_t kWideMinSliceF32Tiled = 131072;
-constexpr size_t kWideLdsBytes = 149 * 1024;  // static LDS of the widest instantiation, rounded up
+constexpr size_t kWideLdsBytes = 153 * 1024;  // static LDS of the widest instantiation (16-bit, dp = 128)
 hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
 // Manhattan / infinity-norm kernel with one query per lane (dp <= 128):
 // `waves` waves of 64 queries per workgroup, each lane with a sorted list of

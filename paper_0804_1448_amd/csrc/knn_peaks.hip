@@ -114,9 +114,53 @@ __global__ __launch_bounds__(256) void mfma_f32_kernel(float* out, uint64_t* clk
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// v_mfma_f32_32x32x16_bf16 with CH independent accumulator chains per wave:
+// how many chains (and waves per SIMD) keep the matrix core busy.
+template <int CH>
+__global__ __launch_bounds__(256) void mfma_chains_kernel(float* out, uint64_t* clk, int iters, float seed) {
+  const int lane = threadIdx.x & 63;
+  bf16x8 a, b;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    a[i] = (__bf16)(seed * (float)(lane + i));
+    b[i] = (__bf16)(seed * (float)(lane - i));
+  }
+  f32x16 c[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) c[j] = f32x16{};
+  stamp(clk, 0);
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) c[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c[j], 0, 0, 0);
+  }
+  stamp(clk, 1);
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < CH; ++j)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += c[j][i];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
 
 extern "C" {
+
+// BF16 32x32x16 loop with `chains` (1, 2, 4 or 8) independent accumulator
+// chains per wave; work per wave and iteration: chains * 32768 flops.
+int knn_peak_launch_chains(int chains, int blocks, int iters, float* out, uint64_t* clk, void* stream) {
+  if (blocks < 1 || iters < 1 || !out || !clk) return (int)hipErrorInvalidValue;
+  const hipStream_t s = (hipStream_t)stream;
+  const float seed = 1.0f / 1024.0f;
+  switch (chains) {
+    case 1: hipLaunchKernelGGL(mfma_chains_kernel<1>, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
+    case 2: hipLaunchKernelGGL(mfma_chains_kernel<2>, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
+    case 4: hipLaunchKernelGGL(mfma_chains_kernel<4>, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
+    case 8: hipLaunchKernelGGL(mfma_chains_kernel<8>, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  return (int)hipGetLastError();
+}
 
 // Launch micro-benchmark `which` (0 vector ALU, 1 BF16 matrix, 2 float32
 // matrix) with `blocks` workgroups of 256 lanes, `iters` iterations each, on

@@ -106,7 +106,8 @@ struct Request {
 // finalized with its own k and k' = k + s, so its result is the one it gets
 // alone.
 struct Batch {
-  int set = 0;
+  int set = 0;           // the set of every request (one-set batches) or of the head (multi-set batches)
+  bool multi = false;    // requests of any set in one launch of the 32x32-tile kernel
   int k = 0;             // largest k of the batch
   int64_t n = 0;
   int64_t outs = 0;      // sum of n * k over the requests
@@ -126,6 +127,7 @@ struct knn_server_s {
   uint32_t magic = 0x6b6e6e53u;
   knn_server_config_t cfg{};
   bool dry = false;
+  bool multi = false;  // 16-bit sets: a batch takes waiting requests of every set
   std::vector<knn_refs_t> sets;
   int device = 0;
   int d = 0;  // dimension of the sets
@@ -157,6 +159,26 @@ bool valid_server(knn_server_t s) { return s && s->magic == 0x6b6e6e53u; }
 
 int64_t set_m(const knn_server_s& s, int set) { return s.dry ? s.cfg.dry_m : s.sets[set]->m; }
 
+// extra candidates of the server's searches
+int server_extra(const knn_server_s& s) { return s.cfg.s_extra < 0 ? (s.cfg.precision == KNN_FP32 ? 8 : 32) : s.cfg.s_extra; }
+
+// the multi-set search requests of batch b: each request's rows of the
+// concatenated queries, its own k and k' = k + s, its slice of the outputs
+std::vector<MultiReq> multi_reqs(const knn_server_s& s, const Batch& b, const float* qd, float* dd, int32_t* id) {
+  std::vector<MultiReq> mr;
+  mr.reserve(b.reqs.size());
+  int64_t row0 = 0, out0 = 0;
+  for (Request* r : b.reqs) {
+    const int64_t m = s.sets[r->set]->m;
+    mr.push_back(MultiReq{s.sets[r->set], row0, r->n, r->k, (int)std::min<int64_t>(m, (int64_t)r->k + server_extra(s)),
+                          dd ? dd + out0 : (float*)16, id ? id + out0 : (int32_t*)16});
+    row0 += r->n;
+    out0 += r->n * r->k;
+  }
+  (void)qd;
+  return mr;
+}
+
 // device bytes of a batch: queries, outputs and the search workspace
 int batch_sizes(knn_server_s& s, Batch& b) {
   b.q_bytes = align_up(b.n * s.d * 4, 256);
@@ -168,6 +190,16 @@ int batch_sizes(knn_server_s& s, Batch& b) {
     // the workspace a real search of this shape would take
     const int64_t kp = std::min<int64_t>(set_m(s, b.set), b.k + (s.cfg.s_extra < 0 ? 32 : s.cfg.s_extra));
     b.ws_bytes = align_up(b.n * align_up(s.d, 32) * 2, 256) + align_up(b.n * 2 * kp * 8, 256);
+    return KNN_OK;
+  }
+  if (b.multi) {
+    std::vector<MultiReq> mr = multi_reqs(s, b, nullptr, nullptr, nullptr);
+    size_t need = 0, tneed = 0;
+    int st = run_multi_ws(mr.data(), (int)mr.size(), (const float*)16, s.cfg.precision, nullptr, 0, &need, nullptr,
+                          &tneed, nullptr);
+    if (st != KNN_OK) return st;
+    b.ws_bytes = align_up((int64_t)need, 256);
+    b.t_bytes = align_up((int64_t)tneed, 256);
     return KNN_OK;
   }
   SearchArgs a;
@@ -184,9 +216,6 @@ int batch_sizes(knn_server_s& s, Batch& b) {
 
 int64_t batch_dev_bytes(const Batch& b) { return b.q_bytes + b.d_bytes + b.i_bytes + b.ws_bytes; }
 int64_t batch_pin_bytes(const Batch& b) { return b.q_bytes + b.d_bytes + b.i_bytes + b.t_bytes; }
-
-// extra candidates of the server's searches
-int server_extra(const knn_server_s& s) { return s.cfg.s_extra < 0 ? (s.cfg.precision == KNN_FP32 ? 8 : 32) : s.cfg.s_extra; }
 
 // Grow slot's pinned staging to hold `bytes` (the slot is idle).
 int ensure_pinned(knn_server_s& s, int slot, int64_t bytes) {
@@ -227,24 +256,31 @@ int launch(knn_server_s& s, Batch& b) {
   }
   hipStream_t st = s.streams[b.slot];
   HIP_TRY(hipMemcpyAsync(qd, qp, (size_t)b.n * s.d * 4, hipMemcpyHostToDevice, st), "server H2D");
-  // one finalize instance per request: rows row0.. with the request's own k
-  const int64_t m = s.sets[b.set]->m;
-  const int extra = server_extra(s);
-  std::vector<SubSearch> subs;
-  subs.reserve(b.reqs.size());
-  int64_t row0 = 0, out0 = 0;
-  for (Request* r : b.reqs) {
-    subs.push_back(SubSearch{row0, r->n, r->k, (int)std::min<int64_t>(m, (int64_t)r->k + extra), dd + out0, id + out0});
-    row0 += r->n;
-    out0 += r->n * r->k;
+  if (b.multi) {
+    std::vector<MultiReq> mr = multi_reqs(s, b, qd, dd, id);
+    rc = run_multi_ws(mr.data(), (int)mr.size(), qd, s.cfg.precision, ws, (size_t)b.ws_bytes, nullptr,
+                      pin + b.q_bytes + b.d_bytes + b.i_bytes, nullptr, st);
   }
-  SearchArgs a;
-  rc = refs_search_args(s.sets[b.set], qd, b.n, b.k, KNN_L2, s.cfg.precision, s.cfg.s_extra, dd, id, st, &a);
-  if (rc == KNN_OK) {
-    a.subs = subs.data();
-    a.nsubs = (int)subs.size();
-    a.tables_host = pin + b.q_bytes + b.d_bytes + b.i_bytes;
-    rc = run_search_ws(a, ws, (size_t)b.ws_bytes, nullptr);
+  if (!b.multi) {
+    // one finalize instance per request: rows row0.. with the request's own k
+    const int64_t m = s.sets[b.set]->m;
+    const int extra = server_extra(s);
+    std::vector<SubSearch> subs;
+    subs.reserve(b.reqs.size());
+    int64_t row0 = 0, out0 = 0;
+    for (Request* r : b.reqs) {
+      subs.push_back(SubSearch{row0, r->n, r->k, (int)std::min<int64_t>(m, (int64_t)r->k + extra), dd + out0, id + out0});
+      row0 += r->n;
+      out0 += r->n * r->k;
+    }
+    SearchArgs a;
+    rc = refs_search_args(s.sets[b.set], qd, b.n, b.k, KNN_L2, s.cfg.precision, s.cfg.s_extra, dd, id, st, &a);
+    if (rc == KNN_OK) {
+      a.subs = subs.data();
+      a.nsubs = (int)subs.size();
+      a.tables_host = pin + b.q_bytes + b.d_bytes + b.i_bytes;
+      rc = run_search_ws(a, ws, (size_t)b.ws_bytes, nullptr);
+    }
   }
   if (rc != KNN_OK) return rc;
   HIP_TRY(hipMemcpyAsync(pin + b.q_bytes, dd, (size_t)b.outs * 4, hipMemcpyDeviceToHost, st), "server D2H");
@@ -273,7 +309,7 @@ void copy_results(knn_server_s& s, Batch& b) {
     const int64_t cnt = r->n * (int64_t)r->k;
     if (s.dry) {
       for (int64_t e = 0; e < cnt; ++e) {
-        r->dist[e] = (float)b.set;
+        r->dist[e] = (float)r->set;
         r->idx[e] = (int32_t)(b.seq & 0x7fffffff);
       }
     } else if (b.status == KNN_OK) {
@@ -297,6 +333,13 @@ void complete(knn_server_s& s, Batch& b) {
   s.slot_busy[b.slot] = false;
 }
 
+// whether request r can join a multi-set batch (16-bit server, k + s <= 128)
+bool req_multi(const knn_server_s& s, const Request& r) {
+  if (!s.multi) return false;
+  const int64_t kp = std::min<int64_t>(set_m(s, r.set), (int64_t)r.k + server_extra(s));
+  return s.dry ? kp <= kWideMaxKc : multi_supported(s.sets[r.set], s.cfg.precision, (int)kp);
+}
+
 // A request that heads the queue but waits for arena memory lets later
 // requests that fit go ahead of it for at most this long; after that nothing
 // passes it until memory frees up.
@@ -307,11 +350,12 @@ constexpr auto kHeadBypass = std::chrono::milliseconds(50);
 // the arena.  nullptr when even the head alone does not fit (lock held).
 std::unique_ptr<Batch> try_batch(knn_server_s& s, size_t hi, int slot) {
   Request* head = s.waiting[hi];
+  const bool multi = req_multi(s, *head);
   std::vector<Request*> cand{head};
   int64_t n = head->n;
   for (size_t i = hi + 1; i < s.waiting.size(); ++i) {
     Request* r = s.waiting[i];
-    if (r->set == head->set && n + r->n <= s.cfg.max_batch_queries) {
+    if ((multi ? req_multi(s, *r) : r->set == head->set) && n + r->n <= s.cfg.max_batch_queries) {
       cand.push_back(r);
       n += r->n;
     }
@@ -319,6 +363,7 @@ std::unique_ptr<Batch> try_batch(knn_server_s& s, size_t hi, int slot) {
   while (!cand.empty()) {
     auto b = std::make_unique<Batch>();
     b->set = head->set;
+    b->multi = multi;
     b->reqs = cand;
     for (Request* r : cand) {
       b->n += r->n;
@@ -462,6 +507,10 @@ int knn_server_create(const knn_refs_t* sets, int32_t nsets, const knn_server_co
     s->d = sets[0]->d;
     HIP_TRY(hipGetDevice(&s->device), "hipGetDevice");
   }
+  // 16-bit sets answer batches of every set's requests in one launch when
+  // every request fits that kernel (k + s <= 128 candidates, d <= 128)
+  s->multi = (cfg->precision == KNN_BF16 || cfg->precision == KNN_FP16) && s->d <= kWideMaxDp &&
+             (cfg->flags & KNN_SERVER_ONE_SET) == 0;
   s->dev_arena = std::make_unique<Arena>(cfg->mem_budget);
   s->slot_busy.assign(cfg->max_batches, false);
   s->pinned.assign(cfg->max_batches, nullptr);
@@ -515,6 +564,8 @@ int knn_server_submit(knn_server_t srv, int32_t set, const float* Q_host, int64_
     probe.k = k;
     probe.n = n;
     probe.outs = n * (int64_t)k;
+    probe.reqs = {r.get()};
+    probe.multi = req_multi(*srv, *r);
     std::lock_guard<std::mutex> lock(srv->mu);
     st = batch_sizes(*srv, probe);
     if (st != KNN_OK) return st;

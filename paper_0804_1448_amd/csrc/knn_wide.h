@@ -13,16 +13,17 @@
 //  * the sorted k'-lists live in registers, one key per lane and one
 //    register pair per query (64 registers for 32 queries); only the
 //    candidate buffers stay in LDS, which leaves room for
-//  * more reference tiles in flight: with 16-bit tiles (short steps) the
-//    copy of step s + 2 is issued while step s is scored; float32 steps are
-//    long enough for one step of lookahead;
+//  * more reference tiles in flight: with 16-bit tiles (short steps) two
+//    steps run between workgroup barriers, and the copies of the next two
+//    are issued while they are scored (four tile buffers); float32 steps are
+//    long enough for one step per barrier and one step of lookahead;
 // and the two waves that share a SIMD run their scoring and selection
 // phases in opposite order, so that one wave's selection overlaps the
 // other's matrix instructions.
 //
 // Lane l of a wave owns query 32 * wave + l % 32 and, in each 32x32 output
 // tile, the 16 rows 8 * (r / 4) + 4 * (l / 32) + r % 4 (r = 0..15); the two
-// lanes of a query each keep a segment of candidate keys (24 with 16-bit
+// lanes of a query each keep a segment of candidate keys (20 with 16-bit
 // tiles, 16 with float32 tiles, whose larger staged rows leave less LDS).
 // Scores, keys and the (score, index) order are those of knn_fused.h.
 #pragma once
@@ -53,8 +54,9 @@ template <int KIND, int NKG>
 struct WideGeom {
   static constexpr bool F32 = KIND == TILE_L2_F32;
   static constexpr int ES = F32 ? 4 : 2;                 // element bytes
-  static constexpr int STAGES = F32 ? 2 : 3;             // tiles in flight
-  static constexpr int SUB = F32 ? 16 : 24;              // keys per lane segment
+  static constexpr int GRP = F32 ? 1 : 2;                // steps between barriers
+  static constexpr int STAGES = 2 * GRP;                 // tile buffers: two groups
+  static constexpr int SUB = F32 ? 16 : 20;              // keys per lane segment
   static constexpr int SEG = SUB + 1;                    // padded against bank conflicts
   static constexpr int VPR = NKG * 16 * ES / 16;         // 16-byte slots of a row's data
   static constexpr int RS = VPR + 1;                     // slots per staged row: data + one pad slot
@@ -62,6 +64,7 @@ struct WideGeom {
   static constexpr int TILES_LDS = STAGES * TILE_BYTES;
   static constexpr int NORMS_LDS = STAGES * kStepRefs;   // floats
   static constexpr int BUFS_LDS = kWideWaves * 64 * SEG; // keys
+  static_assert(TILES_LDS + NORMS_LDS * 4 + (size_t)BUFS_LDS * 8 <= kWideLdsBytes, "LDS of one workgroup");
 };
 
 // One work item of the kernel: the queries of block `qblock` of instance
@@ -89,7 +92,6 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   constexpr int TILE_BYTES = G::TILE_BYTES;
   constexpr int NI = RS;                             // wave-wide copy instructions per tile
   constexpr int PER_WAVE = (NI + kWideWaves - 1) / kWideWaves;
-  constexpr int VM_PER_STAGE = PER_WAVE + 1;         // tile slots + norms, per wave
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, c = lane & 31, h = lane >> 5;
@@ -121,26 +123,32 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   // compiler's wait tracking (which cannot always tell the three tile buffers
   // apart) does not add full waits before reads of the other buffers.  They
   // are ordered by the explicit vmcnt waits and the barrier (whose memory
-  // clobber keeps every LDS access on its side).  M0 carries the LDS base of
-  // the wave's 64 destination slots and is restored afterwards.
-  auto copy16 = [](const void* g, void* lds) __attribute__((always_inline)) {
-    const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)lds);  // wave-uniform
+  // clobber keeps every LDS access on its side).  Each copy takes a
+  // wave-uniform 64-bit base in scalar registers and a 32-bit per-lane byte
+  // offset; M0 carries the LDS address of the wave's 64 destination slots
+  // and is restored afterwards.
+  auto copy16 = [](const void* gbase, uint32_t voff, uint32_t lds) __attribute__((always_inline)) {
     uint32_t save;
     asm volatile(
-        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2\n\ts_mov_b32 m0, %0"
         : "=&s"(save)
-        : "v"(g), "s"(la));
+        : "v"(voff), "s"(gbase), "s"(lds));
   };
-  auto copy4 = [](const void* g, void* lds) __attribute__((always_inline)) {
-    const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)lds);  // wave-uniform
+  auto copy4 = [](const void* gbase, uint32_t voff, uint32_t lds) __attribute__((always_inline)) {
     uint32_t save;
     asm volatile(
-        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %3\n\ts_nop 0\n\tglobal_load_lds_dword %1, %2\n\ts_mov_b32 m0, %0"
         : "=&s"(save)
-        : "v"(g), "s"(la));
+        : "v"(voff), "s"(gbase), "s"(lds));
+  };
+  auto uniform_ptr = [](const void* ptr) __attribute__((always_inline)) {
+    const uint64_t v = (uint64_t)(uintptr_t)ptr;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const unsigned char*)(uintptr_t)(((uint64_t)hi << 32) | lo);
   };
 
-  // ---- staging of step `st` into (dst, ndst): copy instruction i fills
+  // ---- staging of a step into tile buffer `b`: copy instruction i fills
   // slots 64i..64i+63; slot j of row r lives at r * RS + j, the pad slot
   // (j = VPR) repeating the row's last data slot.  With a row stride of an
   // odd number of 16-byte slots the operand reads of 8 consecutive rows hit
@@ -148,21 +156,39 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   // one per-lane address.  Every wave issues the same number of copies
   // (instructions past NI repeat earlier ones, and every wave copies the
   // norms: identical bytes to identical places), so one immediate vmcnt
-  // serves all waves.
-  auto stage = [&](int st, unsigned char* dst, float* ndst) __attribute__((always_inline)) {
-    const int64_t rb = s0 + (int64_t)st * kStepRefs;
-    const int rlast = (int)min((int64_t)kStepRefs, s1 - rb) - 1;
-    const unsigned char* gR = (const unsigned char*)in.R + rb * (int64_t)in.ldr * ES;
-    const int rowbytes = in.ldr * ES;
+  // serves all waves.  The per-lane row, byte offset and LDS slot of each
+  // copy are the same for every step; only the last, partial step of a
+  // slice clamps its rows to the slice.
+  const int rowbytes = in.ldr * ES;
+  int crow[PER_WAVE];
+  uint32_t cjo[PER_WAVE], coff[PER_WAVE], clds[PER_WAVE];
 #pragma unroll
-    for (int u = 0; u < PER_WAVE; ++u) {
-      const int i = (wave + kWideWaves * u) % NI;
-      const int s = 64 * i + lane;
-      const int row = s / RS, jp = s - row * RS;
-      const int j = min(jp, VPR - 1);
-      copy16(gR + min(row, rlast) * rowbytes + j * 16, dst + i * 1024);
+  for (int u = 0; u < PER_WAVE; ++u) {
+    const int i = (wave + kWideWaves * u) % NI;
+    const int sl = 64 * i + lane;
+    const int row = sl / RS, jp = sl - row * RS;
+    crow[u] = row;
+    cjo[u] = (uint32_t)min(jp, VPR - 1) * 16;
+    coff[u] = (uint32_t)(row * rowbytes) + cjo[u];
+    clds[u] = __builtin_amdgcn_readfirstlane((uint32_t)i * 1024);
+  }
+  const uint32_t tiles_lds = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)tiles);
+  const uint32_t norms_lds = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)norms);
+  auto stage = [&](int st, int b) __attribute__((always_inline)) {
+    const int64_t rb = s0 + (int64_t)st * kStepRefs;
+    const unsigned char* gR = uniform_ptr((const unsigned char*)in.R + rb * (int64_t)rowbytes);
+    const unsigned char* gN = uniform_ptr(in.rhalf + rb);
+    const uint32_t tl = tiles_lds + (uint32_t)(b * TILE_BYTES), nl = norms_lds + (uint32_t)(b * kStepRefs * 4);
+    if (rb + kStepRefs <= s1) {
+#pragma unroll
+      for (int u = 0; u < PER_WAVE; ++u) copy16(gR, coff[u], tl + clds[u]);
+      copy4(gN, (uint32_t)lane * 4, nl);
+    } else {  // the last, partial step: rows past the slice repeat its last row
+      const int rlast = (int)(s1 - rb) - 1;
+#pragma unroll
+      for (int u = 0; u < PER_WAVE; ++u) copy16(gR, (uint32_t)(min(crow[u], rlast) * rowbytes) + cjo[u], tl + clds[u]);
+      copy4(gN, (uint32_t)min(lane, rlast) * 4, nl);
     }
-    copy4(in.rhalf + rb + min(lane, rlast), ndst);
   };
 
   // ---- selection state
@@ -232,8 +258,7 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
 
   // ---- scoring phase: the 64 references of step `st` against the wave's
   // 32 queries, |r|^2 / 2 preloaded into the accumulators
-  auto score = [&](int st) __attribute__((always_inline)) {
-    const int b = st % STAGES;
+  auto score = [&](int b) __attribute__((always_inline)) {
     const unsigned char* rt = tiles + b * TILE_BYTES;
     const float* nrd = norms + b * kStepRefs;
 #pragma unroll
@@ -327,36 +352,45 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   // (which share the SIMDs with 0-3) first select step s-1 and then score
   // step s, so on each SIMD one wave's selection runs beside the other's
   // matrix instructions.  One extra pass lets waves 4-7 select the last
-  // step.  Each step stages step + STAGES - 1 (near the end of the slice: a
-  // repeat of the last step into a buffer no later step reads, so every
-  // step issues the same copies and waits with one vmcnt), then waits for
-  // step+1's copy.
+  // step.  Steps run in groups of GRP between workgroup barriers: the first
+  // step of a group stages the next group into the other half of the tile
+  // buffers (which every wave finished reading before the last barrier;
+  // near the end of the slice, repeats of the last step into buffers no
+  // later step reads, so every group issues the same copies), and the last
+  // step of a group waits for those copies before the barrier.  With two
+  // steps per barrier a wave whose selection runs long in one step can catch
+  // up in the next before the others wait for it.
   const bool lead = wave < kWideWaves / 2;
-  constexpr int VM_AHEAD = VM_PER_STAGE * (STAGES - 2);  // copies that may stay in flight
+  constexpr int GRP = G::GRP;
   if (nsteps > 0) {
 #pragma unroll
-    for (int i = 0; i < STAGES - 1; ++i) stage(min(i, nsteps - 1), tiles + i * TILE_BYTES, norms + i * kStepRefs);
-    wait_vmem_n<VM_AHEAD>();
+    for (int i = 0; i < GRP; ++i) stage(min(i, nsteps - 1), i);
+    wait_vmem();
     barrier_keep_copies();
   }
+  int bs = 0;   // tile buffer of `step`
+  int gi = 0;   // position of `step` in its group
   for (int step = 0; step <= nsteps; ++step) {
-    if (step < nsteps) {
-      const int b = (step + STAGES - 1) % STAGES;
-      stage(min(step + STAGES - 1, nsteps - 1), tiles + b * TILE_BYTES, norms + b * kStepRefs);
+    if (gi == 0 && step < nsteps) {
+      // group start: stage the next group into the other half of the buffers
+#pragma unroll
+      for (int i = 0; i < GRP; ++i) stage(min(step + GRP + i, nsteps - 1), (bs ^ GRP) + i);
     }
     if (lead) {
       if (step < nsteps) {
-        score(step);
+        score(bs);
         select(step);
       }
     } else {
       if (step > 0) select(step - 1);
-      if (step < nsteps) score(step);
+      if (step < nsteps) score(bs);
     }
-    if (step < nsteps) {
-      wait_vmem_n<VM_AHEAD>();  // step+1's copy has landed; later ones may still run
+    if (step < nsteps && (gi == GRP - 1 || step == nsteps - 1)) {
+      wait_vmem();  // the next group's copies have landed
       barrier_keep_copies();
     }
+    bs = bs == STAGES - 1 ? 0 : bs + 1;
+    gi = gi == GRP - 1 ? 0 : gi + 1;
   }
   {  // end of the slice: flush every buffer
     const uint64_t pend = ballot(lcnt > 0);

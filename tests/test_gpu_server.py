@@ -92,6 +92,35 @@ def test_server_matches_alone_and_oracle(K, precision):
         r.close()
 
 
+@pytest.mark.parametrize("one_set", [False, True])
+def test_server_16bit_sets_mixed_k_match_alone(K, one_set):
+    """FP16 sets: requests with k + 32 <= 128 run in multi-set launches (every
+    set in one launch; one_set=False), k = 100 (k' = 132) in one-set
+    batches; with one_set=True every batch holds one set.  Every request's
+    result is bitwise the search of the request alone."""
+    banner(f"server fp16 mixed k, one_set={one_set}")
+    d = 64
+    sets = make_sets(K, "fp16", [(7000, d), (20000, d), (1500, d)], 5)
+    reqs = requests(len(sets), d, 36, 6, max_n=400, ks=(1, 20, 96, 100))
+    with K.Server([r for _, r in sets], mem_budget=512 << 20, max_batches=2, max_batch_queries=2048,
+                  precision="fp16", one_set=one_set) as srv:
+        tickets = [srv.submit(s, Q, k) for s, Q, k in reqs]
+        got = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["batches"] < len(reqs)
+    hits = slots = 0.0
+    for j, ((s, Q, k), (gd, gi, _)) in enumerate(zip(reqs, got)):
+        wd, wi = alone(sets[s][1], Q, k, "fp16")
+        assert np.array_equal(wd, gd) and np.array_equal(wi, gi), f"request {j} (set {s}, k {k})"
+        rep = compare(Q, sets[s][0], k, "l2", gd, gi, tol=TOL)
+        assert rep["bad_index_rows"] == 0 and rep["bad_pair"] == 0 and rep["max_rel_err_hits"] <= TOL, (j, rep)
+        hits += rep["recall"] * rep["queries"] * rep["k"]
+        slots += rep["queries"] * rep["k"]
+    assert hits / slots >= 0.999, hits / slots
+    for _, r in sets:
+        r.close()
+
+
 def test_server_tight_budget_serialises(K):
     """A budget that holds one request at a time still answers every request."""
     banner("server tight budget")

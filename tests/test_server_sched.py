@@ -78,6 +78,40 @@ def test_batch_mates_share_set_and_respect_max_queries(K):
         assert srv.stats()["batches"] == len(by_batch)
 
 
+def test_16bit_batches_take_every_set(K):
+    """16-bit servers put waiting requests of every set (k + s <= 128) into one
+    launch; k + s > 128 requests, and every request with one_set=True, batch
+    with their own set only.  Each request's dist reads its own set."""
+    with K.Server.dry(3, m=5000, d=D, us_per_query=200.0, max_batches=1, max_batch_queries=200,
+                      precision="fp16") as srv:
+        first = srv.submit(0, q(5), 3)  # occupies the only stream
+        rng = np.random.default_rng(7)
+        subs = []
+        for i in range(40):
+            s, k, n = int(rng.integers(3)), int(rng.choice([3, 50, 100])), int(rng.integers(1, 9))
+            subs.append((srv.submit(s, q(n, i), k), s, n, k))
+        res = wait_all(srv, [first] + [t for t, *_ in subs])
+        by_batch = {}
+        for t, s, n, k in subs:
+            assert np.all(res[t][0] == s)
+            by_batch.setdefault(int(res[t][1][0, 0]), []).append((s, n, k))
+        mixed = 0
+        for members in by_batch.values():
+            big = [k for _, _, k in members if k + 32 > 128]
+            assert not big or len({s for s, _, _ in members}) == 1, members  # k' > 128: a batch of one set
+            mixed += len({s for s, _, _ in members}) > 1
+        assert mixed > 0, "no batch mixed sets"
+    with K.Server.dry(3, m=5000, d=D, us_per_query=200.0, max_batches=1, max_batch_queries=200,
+                      precision="fp16", one_set=True) as srv:
+        first = srv.submit(0, q(5), 3)
+        subs = [(srv.submit(i % 3, q(4, i), 3), i % 3) for i in range(30)]
+        res = wait_all(srv, [first] + [t for t, _ in subs])
+        by_batch = {}
+        for t, s in subs:
+            by_batch.setdefault(int(res[t][1][0, 0]), set()).add(s)
+        assert all(len(v) == 1 for v in by_batch.values())
+
+
 def test_fifo_head_no_starvation(K):
     """With one stream and no batching possible, requests complete in arrival order."""
     with K.Server.dry(2, m=500, d=D, us_per_query=50.0, max_batches=1, max_batch_queries=8) as srv:
