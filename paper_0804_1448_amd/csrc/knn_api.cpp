@@ -262,6 +262,12 @@ int env_int(const char* name) {
   return v ? atoi(v) : 0;
 }
 
+// KNN_SLICE_SHARE=0 turns off the bound a query's slices share (timing comparisons)
+bool slice_share_on() {
+  const char* v = getenv("KNN_SLICE_SHARE");
+  return !(v && atoi(v) == 0);
+}
+
 // tiled_refs: the references can be prepared in the 32-row tile layout (one-shot
 // searches), which makes the float32 lane kernel the faster one up to far longer slices
 int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Plan* out) {
@@ -437,7 +443,10 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   const size_t kbytes = (size_t)round_up(a.n * plan.P * (int64_t)plan.kc * 8, 256);
   const size_t k2bytes = plan.G > 1 ? (size_t)round_up(a.n * plan.P2 * (int64_t)plan.kc * 8, 256) : 0;
   const size_t tbytes = a.nsubs > 0 ? sub_tables_bytes(a.nsubs, a.n) : 0;
-  const size_t total = cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes + k2bytes + tbytes;
+  // the 32x32-tile kernel's slices of one query share their bound
+  const bool share = plan.wide && plan.P > 1 && prep_q && slice_share_on();
+  const size_t sbytes = share ? (size_t)round_up(a.n * 4, 256) : 0;
+  const size_t total = cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes + k2bytes + tbytes + sbytes;
   if (need) *need = total;
   if (!ws_in) return KNN_OK;
   if (ws_size < total) return fail(KNN_ERR_INVALID, "workspace of %zu bytes is smaller than the %zu needed", ws_size, total);
@@ -449,6 +458,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   uint64_t* part = (uint64_t*)(wq + qbytes);
   uint64_t* part2 = (uint64_t*)((unsigned char*)part + kbytes);
   unsigned char* tables = (unsigned char*)part2 + k2bytes;
+  uint32_t* tshare = share ? (uint32_t*)(tables + tbytes) : nullptr;
 
   const void* rows = a.rows;
   int ldr = a.ldr;
@@ -480,7 +490,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   if (prep_q) {
     TimedLaunch tl("prep_queries", a.stream);
     HIP_TRY(launch_prep_rows(a.Q, a.n, a.d, a.d, l2 ? centre : nullptr, wq, plan.dp, elem_of_kind(a.kind), nullptr,
-                             a.stream),
+                             a.stream, nullptr, tshare),
             "query preparation launch");
     qp = wq;
     ldq = plan.dp;
@@ -501,6 +511,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   fi.nchunk = plan.nchunk;
   fi.P = plan.P;
   fi.kc = plan.kc;
+  fi.tshare = tshare;
   fp.insts = nullptr;
   fp.items = nullptr;
   fp.nitems = 0;
@@ -612,7 +623,7 @@ struct MultiPlan {
   struct Req {
     int P = 1, G = 1, P2 = 1;
     int64_t slice_len = 0;
-    size_t q_off = 0, part_off = 0, part2_off = 0;
+    size_t q_off = 0, part_off = 0, part2_off = 0, share_off = 0;
   };
   std::vector<Req> req;
   int dp = 0, kind = 0;
@@ -626,7 +637,7 @@ int multi_plan(const MultiReq* reqs, int nreq, int precision, MultiPlan* out) {
   mp = MultiPlan{};
   mp.kind = tile_kind(KNN_L2, precision);
   mp.req.resize(nreq);
-  // one slice length for the launch: about four items per CU over all the
+  // one slice length for the launch: about two items per CU over all the
   // requests' query blocks, at least 16 steps
   int64_t work = 0;
   for (int i = 0; i < nreq; ++i) {
@@ -638,7 +649,7 @@ int multi_plan(const MultiReq* reqs, int nreq, int precision, MultiPlan* out) {
     work += ceil_div(r.n, (int64_t)kWideQueries) * r.refs->m;
   }
   mp.dp = padded_dim(mp.kind, reqs[0].refs->d);
-  const int64_t target = std::max<int64_t>(16 * kStepRefs, round_up(ceil_div(work, 4 * (int64_t)device_cu_count()),
+  const int64_t target = std::max<int64_t>(16 * kStepRefs, round_up(ceil_div(work, 2 * (int64_t)device_cu_count()),
                                                                      kStepRefs));
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -662,6 +673,7 @@ int multi_plan(const MultiReq* reqs, int nreq, int precision, MultiPlan* out) {
     q.q_off = take((size_t)r.n * mp.dp * 2);
     q.part_off = take((size_t)r.n * q.P * r.kprime * 8);
     if (q.G > 1) q.part2_off = take((size_t)r.n * q.P2 * r.kprime * 8);
+    q.share_off = take((size_t)r.n * 4);
     mp.nitems += ceil_div(r.n, (int64_t)kWideQueries) * q.P;
     mp.nfitems += ceil_div(r.n, (int64_t)kFinalWaves);
   }
@@ -732,6 +744,7 @@ int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, 
     jb.lds = R->d;
     jb.ldd = mp.dp;
     jb.elem = elem;
+    jb.tshare = (uint32_t*)(w + q.share_off);
     prep_rows += r.n;
     FusedInst& fi = insts[i];
     fi = FusedInst{};
@@ -748,6 +761,7 @@ int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, 
     fi.nchunk = 1;
     fi.P = q.P;
     fi.kc = r.kprime;
+    fi.tshare = q.P > 1 && slice_share_on() ? (uint32_t*)(w + q.share_off) : nullptr;
     const int64_t qb = ceil_div(r.n, (int64_t)kWideQueries);
     for (int64_t b = 0; b < qb; ++b)
       for (int sl = 0; sl < q.P; ++sl) {
@@ -803,7 +817,12 @@ int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, 
   fp.cb = 32;
   fp.waves = 8;
   fp.kc_max = kc_max;
-  fp.counter = counter;
+  // Every request has the same padded dimension; with one key per lane for
+  // all of them (k' <= 64) the kernel built for that dimension alone takes
+  // the items, in table order, one per workgroup (fewer registers than the
+  // kernel that serves every dimension and both list sizes); otherwise that
+  // kernel takes them through the counter.
+  fp.counter = kc_max <= kWideMaxKc1 ? nullptr : counter;
   {
     TimedLaunch tl(fused_name(mp.kind), stream);
     HIP_TRY(launch_fused(mp.kind, fp, stream), "multi-set fused launch");
@@ -1238,6 +1257,7 @@ struct BatchInst {
   int64_t slice_len = 0;
   size_t q_off = 0;     // prepared queries in the workspace
   size_t part_off = 0;  // candidate lists in the workspace (sized for the most slices a configuration gives)
+  size_t share_off = 0; // the one-launch group: per-query bound shared by the query's slices
 };
 
 // A launch configuration of a group: (waves, cb) of the general kernel, or
@@ -1249,6 +1269,18 @@ struct GroupConfig {
   int waves = 8;
   int cb = kWideCb;
   int64_t slice = 0;
+  // one-launch group: 0 = one launch of the kernel that serves every padded
+  // dimension and list size; 1 = one launch per (padded dimension, list
+  // size) class of the kernel built for that class alone (fewer registers)
+  int split = 0;
+};
+
+// items of one (padded dimension, keys per lane) class in the item list
+struct ItemRange {
+  int start = 0;
+  int count = 0;
+  int dp = 0;
+  int kc_max = 0;
 };
 
 // Instances sharing one fused launch.  Every 16-bit Euclidean instance with
@@ -1269,6 +1301,7 @@ struct BatchGroup {
   size_t insts_off = 0;    // FusedInst table in the workspace
   size_t items_off = 0;    // FusedItem list (sized for the configuration with the most items)
   int nitems = 0;
+  std::vector<ItemRange> ranges;  // split configuration: the classes' items
   bool tuned = false;
 };
 
@@ -1288,8 +1321,13 @@ std::vector<GroupConfig> group_configs(const BatchGroup& g) {
   if (g.one) {
     // tile shape fixed (256 queries x 64 references per step); the tuner
     // picks the slice length, which sets the number and size of the items
-    for (int64_t s : {g.base_slice, g.base_slice / 2, g.base_slice * 2, g.base_slice / 4})
-      out.push_back({8, kWideCb, clamp_slice(s)});
+    // KNN_BATCH_SPLIT=0 / 1 keeps only the one-launch / the per-class form
+    const char* es = getenv("KNN_BATCH_SPLIT");
+    for (int split : {0, 1}) {
+      if (es && atoi(es) != split) continue;
+      for (int64_t s : {g.base_slice, g.base_slice / 2, g.base_slice * 2, g.base_slice / 4})
+        out.push_back({8, kWideCb, clamp_slice(s), split});
+    }
     return out;
   }
   if (group_wide_ok(g)) out.push_back({8, kWideCb, g.base_slice});
@@ -1321,7 +1359,7 @@ std::string tune_key(const BatchGroup& g, int64_t pairs) {
   }
   char buf[96];
   if (g.one)
-    snprintf(buf, sizeof buf, "v3/one/k%d/s%d", g.kind, bucket);
+    snprintf(buf, sizeof buf, "v4/one/k%d/s%d", g.kind, bucket);
   else
     snprintf(buf, sizeof buf, "v3/k%d/d%d/c%d/s%d", g.kind, g.dp, g.kclass, bucket);
   return buf;
@@ -1389,8 +1427,10 @@ std::pair<int, int64_t> slicing(const BatchInst& in, int64_t slice) {
 
 // items of group g, longest first: cost = query columns of the block x
 // references of the slice x (padded dimension + a fixed selection share)
-std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, const GroupConfig& c) {
+std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, const GroupConfig& c,
+                                   std::vector<ItemRange>* ranges = nullptr) {
   struct Cost {
+    int64_t cls;   // split configuration: (padded dimension, keys per lane) class
     int64_t cost;
     FusedItem it;
   };
@@ -1400,12 +1440,14 @@ std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, co
     const BatchInst& in = b.inst[g.insts[j]];
     const auto sl = slicing(in, c.slice);
     const int64_t qb = ceil_div(in.prob.n, nq);
+    const int64_t cls = c.split ? in.dp * 2 + (in.kc > kWideMaxKc1 ? 1 : 0) : 0;
     for (int64_t q = 0; q < qb; ++q) {
       const int64_t rows = std::min<int64_t>(nq, in.prob.n - q * nq);
       for (int s = 0; s < sl.first; ++s) {
         const int64_t refs = std::min<int64_t>(sl.second, in.prob.refs->m - s * sl.second);
         // a block costs its full width of queries whatever its fill
         Cost e;
+        e.cls = cls;
         e.cost = (int64_t)nq * refs * (in.dp + 64) + rows;
         e.it.inst = (int)j;
         e.it.qblock = (int)q;
@@ -1415,10 +1457,21 @@ std::vector<FusedItem> group_items(const knn_batch_s& b, const BatchGroup& g, co
       }
     }
   }
-  std::stable_sort(all.begin(), all.end(), [](const Cost& x, const Cost& y) { return x.cost > y.cost; });
+  // longest first (within each class when split)
+  std::stable_sort(all.begin(), all.end(), [](const Cost& x, const Cost& y) {
+    return x.cls != y.cls ? x.cls > y.cls : x.cost > y.cost;
+  });
   std::vector<FusedItem> items;
   items.reserve(all.size());
-  for (auto& e : all) items.push_back(e.it);
+  if (ranges) ranges->clear();
+  for (size_t i = 0; i < all.size(); ++i) {
+    items.push_back(all[i].it);
+    if (!ranges || !c.split) continue;
+    const BatchInst& in = b.inst[g.insts[all[i].it.inst]];
+    if (i == 0 || all[i].cls != all[i - 1].cls) ranges->push_back({(int)i, 0, in.dp, 0});
+    ranges->back().count += 1;
+    ranges->back().kc_max = std::max(ranges->back().kc_max, in.kc);
+  }
   return items;
 }
 
@@ -1475,12 +1528,13 @@ int batch_set_group_config(knn_batch_s& b, BatchGroup& g, const GroupConfig& c) 
     fi.nchunk = g.nchunk;
     fi.P = in.P;
     fi.kc = in.kc;
+    fi.tshare = g.one && in.P > 1 && slice_share_on() ? (uint32_t*)(w + in.share_off) : nullptr;
     fis.push_back(fi);
     b.finsts[j].P = in.P;
   }
   int st = upload(w + g.insts_off, fis.data(), fis.size() * sizeof(FusedInst));
   if (st != KNN_OK) return st;
-  std::vector<FusedItem> items = group_items(b, g, c);
+  std::vector<FusedItem> items = group_items(b, g, c, &g.ranges);
   st = upload(w + g.items_off, items.data(), items.size() * sizeof(FusedItem));
   if (st != KNN_OK) return st;
   st = upload(w + b.finsts_off, b.finsts.data(), b.finsts.size() * sizeof(FinalInst));
@@ -1496,6 +1550,26 @@ int batch_set_group_config(knn_batch_s& b, BatchGroup& g, const GroupConfig& c) 
   return KNN_OK;
 }
 
+// Enqueue group g's fused launch(es) on `s`: one launch, or for a split
+// one-launch group one launch per class of the kernel built for it, each
+// taking its items in table order.
+hipError_t group_launch(knn_batch_s& b, BatchGroup& g, hipStream_t s) {
+  FusedParams fp = group_params(b, g);
+  if (!(g.one && g.cfg.split)) return launch_fused(g.kind, fp, s);
+  const FusedItem* base = fp.items;
+  for (const ItemRange& r : g.ranges) {
+    FusedParams f = fp;
+    f.items = base + r.start;
+    f.nitems = r.count;
+    f.ng = r.dp / 16;
+    f.kc_max = r.kc_max;
+    f.counter = nullptr;
+    const hipError_t e = launch_fused(g.kind, f, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Enqueue the whole batch on `s`.
 int batch_enqueue(knn_batch_s& b, hipStream_t s) {
   unsigned char* w = (unsigned char*)b.ws;
@@ -1507,9 +1581,8 @@ int batch_enqueue(knn_batch_s& b, hipStream_t s) {
   }
   for (BatchGroup& g : b.groups) {
     if (g.nitems == 0) continue;
-    FusedParams fp = group_params(b, g);
     TimedLaunch tl(fused_name(g.kind), s);
-    HIP_TRY(launch_fused(g.kind, fp, s), "batched fused launch");
+    HIP_TRY(group_launch(b, g, s), "batched fused launch");
   }
   FinalParams fin{};
   fin.insts = (const FinalInst*)(w + b.finsts_off);
@@ -1560,11 +1633,10 @@ int batch_tune(knn_batch_s& b, hipStream_t s) {
     for (size_t ci = 0; ci < cands.size(); ++ci) {
       st = batch_set_group_config(b, g, cands[ci]);
       if (st != KNN_OK) break;
-      FusedParams fp = group_params(b, g);
       auto one_launch = [&]() {
         hipError_t e = hipSuccess;
         if (g.one) e = hipMemsetAsync(w + b.counter_off, 0, sizeof(int), s);  // outside any graph
-        if (e == hipSuccess) e = launch_fused(g.kind, fp, s);
+        if (e == hipSuccess) e = group_launch(b, g, s);
         return e;
       };
       hipError_t e = one_launch();  // warm-up
@@ -1716,6 +1788,7 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     for (const GroupConfig& c : group_configs(b->groups[in.group])) pmost = std::max(pmost, slicing(in, c.slice).first);
     in.q_off = take((size_t)in.prob.n * in.dp * in.es);
     in.part_off = take((size_t)in.prob.n * pmost * in.kc * 8);
+    in.share_off = b->groups[in.group].one ? take((size_t)in.prob.n * 4) : 0;
   }
   for (BatchGroup& g : b->groups) {
     g.insts_off = take(g.insts.size() * sizeof(FusedInst));
@@ -1752,6 +1825,7 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     jb.lds = r->d;
     jb.ldd = in.dp;
     jb.elem = elem_of_kind(in.kind);
+    jb.tshare = b->groups[in.group].one ? (uint32_t*)(w + in.share_off) : nullptr;
     jobs.push_back(jb);
     row0 += in.prob.n;
     FinalInst fi{};

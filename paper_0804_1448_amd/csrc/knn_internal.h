@@ -55,6 +55,11 @@ struct FusedInst {
   int nchunk;           // ceil(dp / chunk width); the last chunk may be shorter
   int P;                // number of slices
   int kc;               // list capacity = k'
+  // per-query bound shared by the query's slices (monotone score code of a
+  // slice's kc-th best so far, the smallest any slice has published; all
+  // ones at the start), or NULL: a score above some slice's kc-th best
+  // cannot be among the query's kc best over the whole set
+  uint32_t* tshare;
 };
 
 // One workgroup's share of a batched launch.
@@ -132,6 +137,7 @@ struct PrepJob {
   int lds;
   int ldd;
   int elem;
+  uint32_t* tshare;     // per-row shared bounds of the search to reset (all ones), or NULL
 };
 
 constexpr int kFinalWaves = 4;          // queries per finalize workgroup
@@ -143,8 +149,10 @@ constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
 // status of the launch.
 // overflow (16-bit elements only, may be NULL): set to 1 when a finite value
 // rounds to infinity in the element type
+// tshare (may be NULL): per-row shared bounds of the search that follows, set to all ones
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst,
-                            int ldd, int elem, float* rhalf, hipStream_t stream, unsigned* overflow = nullptr);
+                            int ldd, int elem, float* rhalf, hipStream_t stream, unsigned* overflow = nullptr,
+                            uint32_t* tshare = nullptr);
 // float32 rows in the 32-row tile layout [i / 32][t / 4][i % 32][t % 4]
 // (ldd a multiple of 4; dst holds round_up(rows, 32) rows)
 hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds, const float* centre, float* dst,

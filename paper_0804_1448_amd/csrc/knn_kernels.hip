@@ -62,10 +62,12 @@ template <int E, bool TILED = false>
 __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict__ src, int64_t rows, int d,
                                                         int lds, const float* __restrict__ centre,
                                                         void* __restrict__ dst, int ldd,
-                                                        float* __restrict__ rhalf, unsigned* __restrict__ overflow) {
+                                                        float* __restrict__ rhalf, unsigned* __restrict__ overflow,
+                                                        uint32_t* __restrict__ tshare) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= rows) return;
+  if (tshare && lane == 0) tshare[row] = 0xffffffffu;
   const float* s = src + row * (int64_t)lds;
   float acc = 0.f;
   for (int t = lane; t < ldd; t += 64) {
@@ -99,23 +101,23 @@ hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds
                                   int ldd, float* rhalf, hipStream_t stream) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL((prep_rows_kernel<ELEM_F32, true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, src,
-                     rows, d, lds, centre, (void*)dst, ldd, rhalf, (unsigned*)nullptr);
+                     rows, d, lds, centre, (void*)dst, ldd, rhalf, (unsigned*)nullptr, (uint32_t*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst, int ldd,
-                            int elem, float* rhalf, hipStream_t stream, unsigned* overflow) {
+                            int elem, float* rhalf, hipStream_t stream, unsigned* overflow, uint32_t* tshare) {
   if (rows <= 0) return hipSuccess;
   dim3 grid((unsigned)((rows + 3) / 4)), block(256);
   if (elem == ELEM_F32)
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_F32>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf,
-                       (unsigned*)nullptr);
+                       (unsigned*)nullptr, tshare);
   else if (elem == ELEM_BF16)
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_BF16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd,
-                       rhalf, overflow);
+                       rhalf, overflow, tshare);
   else
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_F16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf,
-                       overflow);
+                       overflow, tshare);
   return hipGetLastError();
 }
 
@@ -653,6 +655,7 @@ __global__ __launch_bounds__(256) void prep_batched_kernel(const PrepJob* __rest
   }
   const PrepJob jb = jobs[lo];
   const int64_t row = g - jb.row0;
+  if (jb.tshare && lane == 0) jb.tshare[row] = 0xffffffffu;
   const float* s = jb.src + row * (int64_t)jb.lds;
   float acc = 0.f;
   for (int t = lane; t < jb.ldd; t += 64) {

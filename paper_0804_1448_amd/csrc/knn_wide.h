@@ -246,9 +246,12 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       }
       Llo[j] = (uint32_t)m;
       Lhi[j] = (uint32_t)(m >> 32);
+      // publish the slice's kc-th best to the query's other slices (an atomic
+      // without return: nothing waits for it)
+      if (in.tshare && kth != 0xffffffffu && lane == 0 && q0 + j < in.n) atomicMin(in.tshare + q0 + j, kth);
       if (c == j) {
         lcnt = 0;
-        thr = kth == 0xffffffffu ? __builtin_huge_valf() : mono_value(kth);
+        if (kth != 0xffffffffu) thr = fminf(thr, mono_value(kth));
       }
     }
     wave_sync();
@@ -388,6 +391,13 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
     if (step < nsteps && (gi == GRP - 1 || step == nsteps - 1)) {
       wait_vmem();  // the next group's copies have landed
       barrier_keep_copies();
+      // every 32 steps the lanes of a query read the bound its other slices
+      // have published (one load, waited for at once: nothing stays live
+      // across the steps for it)
+      if (in.tshare && (step & 31) == 31 && qrow < in.n) {
+        const uint32_t sh = __atomic_load_n(in.tshare + qrow, __ATOMIC_RELAXED);
+        if (sh != 0xffffffffu) thr = fminf(thr, mono_value(sh));
+      }
     }
     bs = bs == STAGES - 1 ? 0 : bs + 1;
     gi = gi == GRP - 1 ? 0 : gi + 1;

@@ -103,7 +103,8 @@ def test_batched_one_launch_equals_per_group_launches(K, precision):
     """All 16-bit instances with k' <= 128 and d <= 128 run in one launch of
     the 32x32-tile kernel (one workgroup per item, items taken longest first
     through a counter).  Its results must equal, bit for bit, those of
-    per-group launches (KNN_BATCH_ONE=-1) and of single searches, for every
+    per-group launches (KNN_BATCH_ONE=-1), of one launch per (padded width,
+    list size) class (KNN_BATCH_SPLIT=1) and of single searches, for every
     padded width and for lists of one and two keys per lane."""
     import os
 
@@ -120,10 +121,16 @@ def test_batched_one_launch_equals_per_group_launches(K, precision):
         per_group = as_np(K.search_batched(probs, precision, s_extra=28))
     finally:
         del os.environ["KNN_BATCH_ONE"]
+    os.environ["KNN_BATCH_SPLIT"] = "1"  # one launch per (padded width, list size) class
+    try:
+        split = as_np(K.search_batched(probs, precision, s_extra=28))
+    finally:
+        del os.environ["KNN_BATCH_SPLIT"]
     hits = slots = 0.0
-    for j, (it, (wd, wi), (od, oi), (gd, gi)) in enumerate(zip(inst, want, one, per_group)):
+    for j, (it, (wd, wi), (od, oi), (gd, gi), (sd, si)) in enumerate(zip(inst, want, one, per_group, split)):
         assert np.array_equal(wd, od) and np.array_equal(wi, oi), f"instance {j}: one launch vs single"
         assert np.array_equal(gd, od) and np.array_equal(gi, oi), f"instance {j}: one launch vs per group"
+        assert np.array_equal(sd, od) and np.array_equal(si, oi), f"instance {j}: one launch vs per class"
         rep = compare(it["Q"], it["R"], it["k"], "l2", od, oi, tol=TOL)
         assert rep["bad_index_rows"] == 0 and rep["bad_pair"] == 0 and rep["max_rel_err_hits"] <= TOL, (j, rep)
         hits += rep["recall"] * rep["queries"] * rep["k"]

@@ -203,3 +203,25 @@ def test_wide_two_keys_integer_grid_is_exact(K, prec):
     D, I = oracle.knn(Q, R, k, "l2")
     assert np.array_equal(idx, I.astype(np.int32))
     assert np.array_equal(dist, D.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_wide_slices_sharing_a_bound_equal_one_slice(K, prec):
+    """Slices of one query publish their k'-th best and filter with the
+    smallest any of them has published.  That bound drops only candidates that
+    cannot be among the query's k' best of the whole set, so 1, 16, 64 and 256
+    slices (KNN_FUSED_P) must give bitwise the same result."""
+    banner(f"wide shared bound {prec}")
+    Q, R = data("gmm", 300, 200000, 64, 811)
+    k = 32
+    out = {}
+    for P in (1, 16, 64, 256):
+        os.environ["KNN_FUSED_P"] = str(P)
+        try:
+            out[P] = search16(K, Q, R, k, prec)
+        finally:
+            del os.environ["KNN_FUSED_P"]
+    check(Q, R, k, *out[1])
+    for P in (16, 64, 256):
+        assert np.array_equal(out[P][1], out[1][1]), f"indices differ with {P} slices"
+        assert np.array_equal(out[P][0].view(np.uint32), out[1][0].view(np.uint32)), f"distances differ with {P} slices"
