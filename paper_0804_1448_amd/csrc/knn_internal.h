@@ -179,6 +179,7 @@ constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice wo
 constexpr int64_t kWideMinSliceF32Tiled = 131072;
 constexpr size_t kWideLdsBytes = 153 * 1024;  // static LDS of the widest instantiation (16-bit, dp = 128)
 hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
+hipError_t launch_wide_f32(const FusedParams& p, hipStream_t stream);  // float32 tiles (knn_wide_f32.hip)
 // Manhattan / infinity-norm kernel with one query per lane (dp <= 128):
 // `waves` waves of 64 queries per workgroup, each lane with a sorted list of
 // kc keys and a queue of `cb` (8 or 12) keys in LDS

@@ -79,12 +79,16 @@ __device__ __forceinline__ void sort_queue(uint64_t (&x)[T]) {
 // search along the merge path; the two sorted runs are then merged in place
 // from the back, which stops once the queue run is used up (the rest of
 // the list is already in place).
-template <int T>
+// RAW_HI: the queue keys hold the float score bits in their high word (the
+// float32 Euclidean kernel appends them so); the merge maps them to the
+// monotone code first.
+template <int T, bool RAW_HI = false>
 __device__ __forceinline__ void lane_merge(uint64_t* L, uint64_t* X, int& len, int& qn, int kc) {
   uint64_t x[T];
 #pragma unroll
   for (int s = 0; s < T; ++s) {
-    const uint64_t v = X[s * kWaveSize];  // slots past the count hold stale keys
+    uint64_t v = X[s * kWaveSize];  // slots past the count hold stale keys
+    if constexpr (RAW_HI) v = ((uint64_t)mono_code(__uint_as_float((uint32_t)(v >> 32))) << 32) | (uint32_t)v;
     x[s] = s < qn ? v : kEmptyKey;
   }
   sort_queue<T>(x);

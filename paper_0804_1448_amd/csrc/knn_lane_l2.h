@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
   const int ki = kc / 2, kj = kc - kc / 2;  // the split of the two-list bound
 
   auto merge = [&]() __attribute__((always_inline)) {
-    lane_merge<T>(L, X, len, qn, kc);
+    lane_merge<T, true>(L, X, len, qn, kc);
     __builtin_amdgcn_wave_barrier();
     const int plen = (int)xor_lane32<32>((uint32_t)len, lane);
     uint32_t t = thr;
@@ -146,10 +146,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
 #pragma unroll
       for (int i = 0; i < 4; ++i) pass[i] = acc[4 * g + i] <= thr_f;
       if (__builtin_amdgcn_ballot_w64(pass[0] || pass[1] || pass[2] || pass[3])) {
-        // branch-free append (a failing key is overwritten or lies past the count)
+        // branch-free append (a failing key is overwritten or lies past the
+        // count); the high word holds the score's float bits, mapped to the
+        // monotone code by the merge
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          X[qn * kWaveSize] = ((uint64_t)mono_code(acc[4 * g + i]) << 32) | (rb + (uint32_t)i);
+          X[qn * kWaveSize] = ((uint64_t)__float_as_uint(acc[4 * g + i]) << 32) | (rb + (uint32_t)i);
           qn += pass[i] ? 1 : 0;
         }
         if (__builtin_amdgcn_ballot_w64(qn > T - 4)) merge();

@@ -74,7 +74,7 @@ struct WideGeom {
 // them that a later item reads.
 // NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG; even
 // for the 16-bit kinds, whose rows are padded to 32).
-template <int KIND, int NKG, int LK>
+template <int KIND, int NKG, int LK, bool SHARE>
 __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int slice, unsigned char* tiles,
                                           float* norms, uint64_t* bufs) {
   static_assert(KIND == TILE_L2_F32 || KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "Euclidean tiles only");
@@ -248,7 +248,8 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       Lhi[j] = (uint32_t)(m >> 32);
       // publish the slice's kc-th best to the query's other slices (an atomic
       // without return: nothing waits for it)
-      if (in.tshare && kth != 0xffffffffu && lane == 0 && q0 + j < in.n) atomicMin(in.tshare + q0 + j, kth);
+      if constexpr (SHARE)
+        if (in.tshare && kth != 0xffffffffu && lane == 0 && q0 + j < in.n) atomicMin(in.tshare + q0 + j, kth);
       if (c == j) {
         lcnt = 0;
         if (kth != 0xffffffffu) thr = fminf(thr, mono_value(kth));
@@ -262,6 +263,9 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   // ---- scoring phase: the 64 references of step `st` against the wave's
   // 32 queries, |r|^2 / 2 preloaded into the accumulators
   auto score = [&](int b) __attribute__((always_inline)) {
+    // a wave issuing matrix instructions goes first on its SIMD, so the other
+    // wave's selection fills the gaps rather than delaying them
+    __builtin_amdgcn_s_setprio(2);
     const unsigned char* rt = tiles + b * TILE_BYTES;
     const float* nrd = norms + b * kStepRefs;
 #pragma unroll
@@ -306,6 +310,7 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
     __builtin_amdgcn_sched_group_barrier(0x008, MPR * PF, 0);
+    __builtin_amdgcn_s_setprio(0);
   };
 
   // ---- selection phase over the scores of step `st` (in acc).  Before a
@@ -394,9 +399,11 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       // every 32 steps the lanes of a query read the bound its other slices
       // have published (one load, waited for at once: nothing stays live
       // across the steps for it)
-      if (in.tshare && (step & 31) == 31 && qrow < in.n) {
-        const uint32_t sh = __atomic_load_n(in.tshare + qrow, __ATOMIC_RELAXED);
-        if (sh != 0xffffffffu) thr = fminf(thr, mono_value(sh));
+      if constexpr (SHARE) {
+        if (in.tshare && (step & 31) == 31 && qrow < in.n) {
+          const uint32_t sh = __atomic_load_n(in.tshare + qrow, __ATOMIC_RELAXED);
+          if (sh != 0xffffffffu) thr = fminf(thr, mono_value(sh));
+        }
       }
     }
     bs = bs == STAGES - 1 ? 0 : bs + 1;
@@ -422,7 +429,7 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
 
 // One instance per launch: grid (query blocks, slices) of p.one, or one item
 // of p.items per workgroup.
-template <int KIND, int NKG>
+template <int KIND, int NKG, bool SHARE>
 __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
   using G = WideGeom<KIND, NKG>;
   __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
@@ -431,14 +438,14 @@ __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
   if (p.items) {
     const FusedItem it = p.items[blockIdx.x];
     const FusedInst in = p.insts[it.inst];
-    wide_item<KIND, NKG, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+    wide_item<KIND, NKG, 1, SHARE>(in, it.qblock, it.slice, tiles, norms, bufs);
   } else {
-    wide_item<KIND, NKG, 1>(p.one, blockIdx.x, blockIdx.y, tiles, norms, bufs);
+    wide_item<KIND, NKG, 1, SHARE>(p.one, blockIdx.x, blockIdx.y, tiles, norms, bufs);
   }
 }
 
 // The same with two keys per lane (k' <= 128; 16-bit tiles).
-template <int KIND, int NKG>
+template <int KIND, int NKG, bool SHARE>
 __global__ __launch_bounds__(512) void wide2_kernel(FusedParams p) {
   using G = WideGeom<KIND, NKG>;
   __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
@@ -447,9 +454,9 @@ __global__ __launch_bounds__(512) void wide2_kernel(FusedParams p) {
   if (p.items) {
     const FusedItem it = p.items[blockIdx.x];
     const FusedInst in = p.insts[it.inst];
-    wide_item<KIND, NKG, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+    wide_item<KIND, NKG, 2, SHARE>(in, it.qblock, it.slice, tiles, norms, bufs);
   } else {
-    wide_item<KIND, NKG, 2>(p.one, blockIdx.x, blockIdx.y, tiles, norms, bufs);
+    wide_item<KIND, NKG, 2, SHARE>(p.one, blockIdx.x, blockIdx.y, tiles, norms, bufs);
   }
 }
 
@@ -477,36 +484,43 @@ __global__ __launch_bounds__(512) void wide_batch_kernel(FusedParams p) {
   const bool two = in.kc > kWideMaxKc1;
   switch (in.dp) {
     case 32:
-      if (two) wide_item<KIND, 2, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 2, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 2, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 2, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
     case 64:
-      if (two) wide_item<KIND, 4, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 4, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 4, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 4, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
     case 96:
-      if (two) wide_item<KIND, 6, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 6, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 6, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 6, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
     default:
-      if (two) wide_item<KIND, 8, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 8, 1>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 8, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 8, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
   }
 }
 
+// The instantiation with the shared-bound code serves item launches and
+// single searches whose slices share a bound; single searches of one slice
+// per query take the one without it (which runs faster: fewer registers).
 template <int KIND, int NKG>
 hipError_t launch_wide_one(const FusedParams& p, hipStream_t stream) {
   if (p.items && p.nitems <= 0) return hipSuccess;
   dim3 grid = p.items ? dim3((unsigned)p.nitems)
                       : dim3((unsigned)((p.one.n + kWideQueriesWG - 1) / kWideQueriesWG), (unsigned)p.one.P);
+  const bool share = p.items != nullptr || p.one.tshare != nullptr;
+  const dim3 block(kWideWaves * kWaveSize);
   if constexpr (KIND != TILE_L2_F32) {
     if (p.kc_max > kWideMaxKc1) {
-      hipLaunchKernelGGL((wide2_kernel<KIND, NKG>), grid, dim3(kWideWaves * kWaveSize), 0, stream, p);
+      if (share) hipLaunchKernelGGL((wide2_kernel<KIND, NKG, true>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((wide2_kernel<KIND, NKG, false>), grid, block, 0, stream, p);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((wide_kernel<KIND, NKG>), grid, dim3(kWideWaves * kWaveSize), 0, stream, p);
+  if (share) hipLaunchKernelGGL((wide_kernel<KIND, NKG, true>), grid, block, 0, stream, p);
+  else hipLaunchKernelGGL((wide_kernel<KIND, NKG, false>), grid, block, 0, stream, p);
   return hipGetLastError();
 }
 
