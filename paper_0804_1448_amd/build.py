@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "libknn.so")
 # measurement only (the benchmark's peak-rate micro-kernels), not the k-NN ABI
 PEAKS_SRC = "knn_peaks.hip"
 PEAKS_LIB = os.path.join(PKG, "libknn_peaks.so")
-SOURCES = ["knn_kernels.hip", "knn_api.cpp", "knn_server.cpp", "knn_noalloc.hip", "knn_wide.hip", "knn_wide_f32.hip", "knn_lane.hip", "knn_lane_l2.hip"] + [
+SOURCES = ["knn_kernels.hip", "knn_api.cpp", "knn_server.cpp", "knn_noalloc.hip", "knn_wide.hip", "knn_wide_bf16.hip", "knn_wide_f16.hip", "knn_wide_f32.hip", "knn_lane.hip", "knn_lane_l2.hip"] + [
     f"knn_fused_{unit}_{v}.hip" for unit in ("f32lo", "f32hi", "bf16", "f16", "l1", "linf") for v in ("s", "l")]
 
 # Packed float32 instructions are disabled on purpose: the compiler emits

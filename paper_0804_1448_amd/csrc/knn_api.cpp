@@ -268,6 +268,30 @@ bool slice_share_on() {
   return !(v && atoi(v) == 0);
 }
 
+// KNN_RANK_SHARE=0 turns off the rank slots of a query's slices (timing comparisons)
+bool rank_share_on() {
+  const char* v = getenv("KNN_RANK_SHARE");
+  return !(v && atoi(v) == 0);
+}
+
+// The rank slots of an instance whose queries are split over P slices (see
+// FusedInst::tshare): each slice publishes its r-th best, r = ceil(kc / P)
+// (at least ceil(kc / 64), so that a group spans at most 64 slices and the
+// r-th key lies in the first 64 of a list); gs = ceil(kc / r) slices make a
+// group (gs * r >= kc, gs <= P) and up to 4 groups are read.
+void set_rank_plan(FusedInst& fi) {
+  fi.rank_r = fi.rank_gs = fi.rank_G = 0;
+  if (!fi.tshare || fi.P < kRankMinSlices || !rank_share_on()) return;
+  const int r = (int)std::max(ceil_div((int64_t)fi.kc, (int64_t)fi.P), ceil_div((int64_t)fi.kc, (int64_t)64));
+  const int gs = (int)ceil_div((int64_t)fi.kc, (int64_t)r);
+  fi.rank_r = r;
+  fi.rank_gs = gs;
+  fi.rank_G = std::max(1, std::min(fi.P / gs, 4));
+}
+
+// workspace bytes of the shared bounds and rank slots of n queries over P slices
+size_t share_bytes(int64_t n, int P) { return (size_t)n * 4 * (1 + (size_t)P); }
+
 // tiled_refs: the references can be prepared in the 32-row tile layout (one-shot
 // searches), which makes the float32 lane kernel the faster one up to far longer slices
 int make_plan(int kind, int64_t n, int64_t m, int d, int kc, bool tiled_refs, Plan* out) {
@@ -445,7 +469,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   const size_t tbytes = a.nsubs > 0 ? sub_tables_bytes(a.nsubs, a.n) : 0;
   // the 32x32-tile kernel's slices of one query share their bound
   const bool share = plan.wide && plan.P > 1 && prep_q && slice_share_on();
-  const size_t sbytes = share ? (size_t)round_up(a.n * 4, 256) : 0;
+  const size_t sbytes = share ? (size_t)round_up((int64_t)share_bytes(a.n, plan.P), 256) : 0;
   const size_t total = cbytes + pbytes0 + rbytes + hbytes + qbytes + kbytes + k2bytes + tbytes + sbytes;
   if (need) *need = total;
   if (!ws_in) return KNN_OK;
@@ -459,6 +483,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   uint64_t* part2 = (uint64_t*)((unsigned char*)part + kbytes);
   unsigned char* tables = (unsigned char*)part2 + k2bytes;
   uint32_t* tshare = share ? (uint32_t*)(tables + tbytes) : nullptr;
+  const int nslots = share && rank_share_on() ? plan.P : 0;
 
   const void* rows = a.rows;
   int ldr = a.ldr;
@@ -490,7 +515,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   if (prep_q) {
     TimedLaunch tl("prep_queries", a.stream);
     HIP_TRY(launch_prep_rows(a.Q, a.n, a.d, a.d, l2 ? centre : nullptr, wq, plan.dp, elem_of_kind(a.kind), nullptr,
-                             a.stream, nullptr, tshare),
+                             a.stream, nullptr, tshare, nslots),
             "query preparation launch");
     qp = wq;
     ldq = plan.dp;
@@ -512,6 +537,7 @@ int run_search_ws(const SearchArgs& a, void* ws_in, size_t ws_size, size_t* need
   fi.P = plan.P;
   fi.kc = plan.kc;
   fi.tshare = tshare;
+  set_rank_plan(fi);
   fp.insts = nullptr;
   fp.items = nullptr;
   fp.nitems = 0;
@@ -673,7 +699,7 @@ int multi_plan(const MultiReq* reqs, int nreq, int precision, MultiPlan* out) {
     q.q_off = take((size_t)r.n * mp.dp * 2);
     q.part_off = take((size_t)r.n * q.P * r.kprime * 8);
     if (q.G > 1) q.part2_off = take((size_t)r.n * q.P2 * r.kprime * 8);
-    q.share_off = take((size_t)r.n * 4);
+    q.share_off = take(share_bytes(r.n, q.P));
     mp.nitems += ceil_div(r.n, (int64_t)kWideQueries) * q.P;
     mp.nfitems += ceil_div(r.n, (int64_t)kFinalWaves);
   }
@@ -745,6 +771,7 @@ int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, 
     jb.ldd = mp.dp;
     jb.elem = elem;
     jb.tshare = (uint32_t*)(w + q.share_off);
+    jb.nslots = rank_share_on() ? q.P : 0;
     prep_rows += r.n;
     FusedInst& fi = insts[i];
     fi = FusedInst{};
@@ -762,6 +789,7 @@ int run_multi_ws(const MultiReq* reqs, int nreq, const float* Q, int precision, 
     fi.P = q.P;
     fi.kc = r.kprime;
     fi.tshare = q.P > 1 && slice_share_on() ? (uint32_t*)(w + q.share_off) : nullptr;
+    set_rank_plan(fi);
     const int64_t qb = ceil_div(r.n, (int64_t)kWideQueries);
     for (int64_t b = 0; b < qb; ++b)
       for (int sl = 0; sl < q.P; ++sl) {
@@ -1257,7 +1285,8 @@ struct BatchInst {
   int64_t slice_len = 0;
   size_t q_off = 0;     // prepared queries in the workspace
   size_t part_off = 0;  // candidate lists in the workspace (sized for the most slices a configuration gives)
-  size_t share_off = 0; // the one-launch group: per-query bound shared by the query's slices
+  size_t share_off = 0; // the one-launch group: bounds shared by the query's slices (FusedInst::tshare)
+  int pmost = 1;        // most slices of any configuration the tuner tries (rank slots per query)
 };
 
 // A launch configuration of a group: (waves, cb) of the general kernel, or
@@ -1529,6 +1558,7 @@ int batch_set_group_config(knn_batch_s& b, BatchGroup& g, const GroupConfig& c) 
     fi.P = in.P;
     fi.kc = in.kc;
     fi.tshare = g.one && in.P > 1 && slice_share_on() ? (uint32_t*)(w + in.share_off) : nullptr;
+    set_rank_plan(fi);
     fis.push_back(fi);
     b.finsts[j].P = in.P;
   }
@@ -1788,7 +1818,8 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     for (const GroupConfig& c : group_configs(b->groups[in.group])) pmost = std::max(pmost, slicing(in, c.slice).first);
     in.q_off = take((size_t)in.prob.n * in.dp * in.es);
     in.part_off = take((size_t)in.prob.n * pmost * in.kc * 8);
-    in.share_off = b->groups[in.group].one ? take((size_t)in.prob.n * 4) : 0;
+    in.pmost = pmost;
+    in.share_off = b->groups[in.group].one ? take(share_bytes(in.prob.n, pmost)) : 0;
   }
   for (BatchGroup& g : b->groups) {
     g.insts_off = take(g.insts.size() * sizeof(FusedInst));
@@ -1826,6 +1857,7 @@ int knn_batch_create(const knn_problem_t* probs, int32_t count, int32_t precisio
     jb.ldd = in.dp;
     jb.elem = elem_of_kind(in.kind);
     jb.tshare = b->groups[in.group].one ? (uint32_t*)(w + in.share_off) : nullptr;
+    jb.nslots = jb.tshare && rank_share_on() ? in.pmost : 0;
     jobs.push_back(jb);
     row0 += in.prob.n;
     FinalInst fi{};

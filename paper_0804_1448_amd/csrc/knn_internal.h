@@ -55,11 +55,18 @@ struct FusedInst {
   int nchunk;           // ceil(dp / chunk width); the last chunk may be shorter
   int P;                // number of slices
   int kc;               // list capacity = k'
-  // per-query bound shared by the query's slices (monotone score code of a
-  // slice's kc-th best so far, the smallest any slice has published; all
-  // ones at the start), or NULL: a score above some slice's kc-th best
-  // cannot be among the query's kc best over the whole set
+  // Bounds shared by the slices of a query, or NULL.  tshare[q]: the
+  // smallest kc-th best (monotone score code) any slice of query q has
+  // published.  With rank_r > 0 the rank slots follow, slice-major:
+  // tshare[n + s * n + q] holds slice s's rank_r-th best for query q.  Any
+  // rank_gs slices hold between them at least rank_gs * rank_r >= kc keys at
+  // or below the largest of their slots, so the smallest such maximum over
+  // rank_G groups of consecutive slices bounds the query's kc-th best over
+  // the whole set as well.  All ones (no key yet) at the start.
   uint32_t* tshare;
+  int rank_r;
+  int rank_gs;
+  int rank_G;
 };
 
 // One workgroup's share of a batched launch.
@@ -138,6 +145,7 @@ struct PrepJob {
   int ldd;
   int elem;
   uint32_t* tshare;     // per-row shared bounds of the search to reset (all ones), or NULL
+  int nslots;           // rank slots per row after them (FusedInst::tshare), also reset
 };
 
 constexpr int kFinalWaves = 4;          // queries per finalize workgroup
@@ -149,10 +157,11 @@ constexpr int kFinalMaxCand = 512;      // k' limit of the re-rank
 // status of the launch.
 // overflow (16-bit elements only, may be NULL): set to 1 when a finite value
 // rounds to infinity in the element type
-// tshare (may be NULL): per-row shared bounds of the search that follows, set to all ones
+// tshare (may be NULL): per-row shared bounds of the search that follows and
+// `nslots` rank slots per row after them (FusedInst::tshare), set to all ones
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst,
                             int ldd, int elem, float* rhalf, hipStream_t stream, unsigned* overflow = nullptr,
-                            uint32_t* tshare = nullptr);
+                            uint32_t* tshare = nullptr, int nslots = 0);
 // float32 rows in the 32-row tile layout [i / 32][t / 4][i % 32][t % 4]
 // (ldd a multiple of 4; dst holds round_up(rows, 32) rows)
 hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds, const float* centre, float* dst,
@@ -177,9 +186,12 @@ constexpr int64_t kWideMinSliceF32 = 16384;  // float32 tiles: shortest slice wo
 // float32 lane kernel (measured: the lane kernel wins at slices of 16384 and
 // 19200, the 32x32 kernel at 2^20)
 constexpr int64_t kWideMinSliceF32Tiled = 131072;
+constexpr int kRankMinSlices = 8;  // fewest slices per query for the rank slots (FusedInst::tshare)
 constexpr size_t kWideLdsBytes = 153 * 1024;  // static LDS of the widest instantiation (16-bit, dp = 128)
 hipError_t launch_wide(int kind, const FusedParams& p, hipStream_t stream);
-hipError_t launch_wide_f32(const FusedParams& p, hipStream_t stream);  // float32 tiles (knn_wide_f32.hip)
+hipError_t launch_wide_f32(const FusedParams& p, hipStream_t stream);   // float32 tiles (knn_wide_f32.hip)
+hipError_t launch_wide_bf16(const FusedParams& p, hipStream_t stream);  // BF16 tiles (knn_wide_bf16.hip)
+hipError_t launch_wide_f16(const FusedParams& p, hipStream_t stream);   // FP16 tiles (knn_wide_f16.hip)
 // Manhattan / infinity-norm kernel with one query per lane (dp <= 128):
 // `waves` waves of 64 queries per workgroup, each lane with a sorted list of
 // kc keys and a queue of `cb` (8 or 12) keys in LDS

@@ -63,11 +63,14 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const float* __restrict_
                                                         int lds, const float* __restrict__ centre,
                                                         void* __restrict__ dst, int ldd,
                                                         float* __restrict__ rhalf, unsigned* __restrict__ overflow,
-                                                        uint32_t* __restrict__ tshare) {
+                                                        uint32_t* __restrict__ tshare, int nslots) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= rows) return;
-  if (tshare && lane == 0) tshare[row] = 0xffffffffu;
+  if (tshare) {
+    if (lane == 0) tshare[row] = 0xffffffffu;
+    for (int s = lane; s < nslots; s += 64) tshare[rows + s * rows + row] = 0xffffffffu;
+  }
   const float* s = src + row * (int64_t)lds;
   float acc = 0.f;
   for (int t = lane; t < ldd; t += 64) {
@@ -101,23 +104,24 @@ hipError_t launch_prep_rows_tiled(const float* src, int64_t rows, int d, int lds
                                   int ldd, float* rhalf, hipStream_t stream) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL((prep_rows_kernel<ELEM_F32, true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, src,
-                     rows, d, lds, centre, (void*)dst, ldd, rhalf, (unsigned*)nullptr, (uint32_t*)nullptr);
+                     rows, d, lds, centre, (void*)dst, ldd, rhalf, (unsigned*)nullptr, (uint32_t*)nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_rows(const float* src, int64_t rows, int d, int lds, const float* centre, void* dst, int ldd,
-                            int elem, float* rhalf, hipStream_t stream, unsigned* overflow, uint32_t* tshare) {
+                            int elem, float* rhalf, hipStream_t stream, unsigned* overflow, uint32_t* tshare,
+                            int nslots) {
   if (rows <= 0) return hipSuccess;
   dim3 grid((unsigned)((rows + 3) / 4)), block(256);
   if (elem == ELEM_F32)
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_F32>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf,
-                       (unsigned*)nullptr, tshare);
+                       (unsigned*)nullptr, tshare, nslots);
   else if (elem == ELEM_BF16)
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_BF16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd,
-                       rhalf, overflow, tshare);
+                       rhalf, overflow, tshare, nslots);
   else
     hipLaunchKernelGGL(prep_rows_kernel<ELEM_F16>, grid, block, 0, stream, src, rows, d, lds, centre, dst, ldd, rhalf,
-                       overflow, tshare);
+                       overflow, tshare, nslots);
   return hipGetLastError();
 }
 
@@ -655,7 +659,10 @@ __global__ __launch_bounds__(256) void prep_batched_kernel(const PrepJob* __rest
   }
   const PrepJob jb = jobs[lo];
   const int64_t row = g - jb.row0;
-  if (jb.tshare && lane == 0) jb.tshare[row] = 0xffffffffu;
+  if (jb.tshare) {
+    if (lane == 0) jb.tshare[row] = 0xffffffffu;
+    for (int s = lane; s < jb.nslots; s += 64) jb.tshare[jb.rows + s * jb.rows + row] = 0xffffffffu;
+  }
   const float* s = jb.src + row * (int64_t)jb.lds;
   float acc = 0.f;
   for (int t = lane; t < jb.ldd; t += 64) {

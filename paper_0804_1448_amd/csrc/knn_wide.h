@@ -74,7 +74,7 @@ struct WideGeom {
 // them that a later item reads.
 // NKG: 16-dimension k groups of the padded dimension (dp = 16 * NKG; even
 // for the 16-bit kinds, whose rows are padded to 32).
-template <int KIND, int NKG, int LK, bool SHARE>
+template <int KIND, int NKG, int LK, int SHARE>
 __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int slice, unsigned char* tiles,
                                           float* norms, uint64_t* bufs) {
   static_assert(KIND == TILE_L2_F32 || KIND == TILE_L2_BF16 || KIND == TILE_L2_F16, "Euclidean tiles only");
@@ -208,6 +208,36 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   uint64_t* myseg = bufs + (size_t)(wave * 64 + lane) * SEG;
   const uint64_t* wbufs = bufs + (size_t)wave * 64 * SEG;
 
+  // The rank bound of this lane's query: for each of rank_G groups of
+  // rank_gs consecutive slices, the largest of their rank slots (the two
+  // lane halves read half a group each), and the smallest of those maxima.
+  // Loads go out eight at a time (four with two-key lists) before any is
+  // waited for.
+  auto rank_bound = [&]() __attribute__((always_inline)) -> uint32_t {
+    constexpr int RL = LK == 1 ? 8 : 4;
+    const int gs = in.rank_gs, half = (gs + 1) >> 1, cnt = h ? gs - half : half;
+    const uint32_t* sl = in.tshare + in.n * (int64_t)(1 + h * half) + qsafe;  // slot of slice h * half
+    uint32_t best = 0xffffffffu;
+    for (int g = 0; g < in.rank_G; ++g) {
+      uint32_t mx = 0;
+      for (int i0 = 0; i0 < cnt; i0 += RL) {
+        uint32_t v[RL];
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+          v[i] = 0;
+          if (i0 + i < cnt)
+            v[i] = __hip_atomic_load(sl + (int64_t)(g * gs + i0 + i) * in.n, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int i = 0; i < RL; ++i) mx = max(mx, v[i]);
+      }
+      mx = max(mx, xor_lane32<32>(mx, lane));
+      best = min(best, mx);
+    }
+    return qrow < in.n ? best : 0xffffffffu;
+  };
+
   // merge the buffers of the queries in `qm` (bit j = query j of the wave)
   // into their lists; refresh the threshold and count of their two lanes
   auto merge_queries = [&](uint32_t qm) __attribute__((always_inline)) {
@@ -247,9 +277,19 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       Llo[j] = (uint32_t)m;
       Lhi[j] = (uint32_t)(m >> 32);
       // publish the slice's kc-th best to the query's other slices (an atomic
-      // without return: nothing waits for it)
-      if constexpr (SHARE)
+      // without return: nothing waits for it), and its rank_r-th best to its
+      // rank slot (a store that bypasses the XCD's L2, as the loads that read it)
+      if constexpr (SHARE >= 1)
         if (in.tshare && kth != 0xffffffffu && lane == 0 && q0 + j < in.n) atomicMin(in.tshare + q0 + j, kth);
+      if constexpr (SHARE == 2) {
+        if (in.tshare && in.rank_r > 0) {
+          const uint32_t rv = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_readfirstlane(in.rank_r - 1));
+          if (rv != 0xffffffffu && lane == 0 && q0 + j < in.n)
+            __hip_atomic_store(in.tshare + in.n * (1 + (int64_t)slice) + q0 + j, rv, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
       if (c == j) {
         lcnt = 0;
         if (kth != 0xffffffffu) thr = fminf(thr, mono_value(kth));
@@ -396,13 +436,23 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
     if (step < nsteps && (gi == GRP - 1 || step == nsteps - 1)) {
       wait_vmem();  // the next group's copies have landed
       barrier_keep_copies();
-      // every 32 steps the lanes of a query read the bound its other slices
-      // have published (one load, waited for at once: nothing stays live
-      // across the steps for it)
-      if constexpr (SHARE) {
+      // the lanes of a query read the bounds its other slices have published
+      // (waited for at once: nothing stays live across the steps for them):
+      // the smallest kc-th best every 32 steps, and the rank bound after
+      // steps 2^i - 1, when a slice's own list is young and the bound of the
+      // other slices' keys matters most
+      if constexpr (SHARE == 1) {
         if (in.tshare && (step & 31) == 31 && qrow < in.n) {
-          const uint32_t sh = __atomic_load_n(in.tshare + qrow, __ATOMIC_RELAXED);
+          const uint32_t sh = __hip_atomic_load(in.tshare + qrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (sh != 0xffffffffu) thr = fminf(thr, mono_value(sh));
+        }
+      } else if constexpr (SHARE == 2) {
+        if (in.tshare && ((step & 31) == 31 || ((step + 1) & step) == 0)) {
+          uint32_t b = 0xffffffffu;
+          if (in.rank_r > 0 && ((step + 1) & step) == 0) b = rank_bound();
+          if ((step & 31) == 31 && qrow < in.n)
+            b = min(b, __hip_atomic_load(in.tshare + qrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (b != 0xffffffffu) thr = fminf(thr, mono_value(b));
         }
       }
     }
@@ -428,8 +478,9 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
 }
 
 // One instance per launch: grid (query blocks, slices) of p.one, or one item
-// of p.items per workgroup.
-template <int KIND, int NKG, bool SHARE>
+// of p.items per workgroup.  SHARE: 0 no bound shared between a query's
+// slices, 1 the smallest kc-th best, 2 that and the rank slots.
+template <int KIND, int NKG, int SHARE>
 __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
   using G = WideGeom<KIND, NKG>;
   __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
@@ -445,7 +496,7 @@ __global__ __launch_bounds__(512) void wide_kernel(FusedParams p) {
 }
 
 // The same with two keys per lane (k' <= 128; 16-bit tiles).
-template <int KIND, int NKG, bool SHARE>
+template <int KIND, int NKG, int SHARE>
 __global__ __launch_bounds__(512) void wide2_kernel(FusedParams p) {
   using G = WideGeom<KIND, NKG>;
   __shared__ __align__(16) unsigned char tiles[G::TILES_LDS];
@@ -484,44 +535,59 @@ __global__ __launch_bounds__(512) void wide_batch_kernel(FusedParams p) {
   const bool two = in.kc > kWideMaxKc1;
   switch (in.dp) {
     case 32:
-      if (two) wide_item<KIND, 2, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 2, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 2, 2, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 2, 1, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
     case 64:
-      if (two) wide_item<KIND, 4, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 4, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 4, 2, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 4, 1, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
     case 96:
-      if (two) wide_item<KIND, 6, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 6, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 6, 2, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 6, 1, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
     default:
-      if (two) wide_item<KIND, 8, 2, true>(in, it.qblock, it.slice, tiles, norms, bufs);
-      else wide_item<KIND, 8, 1, true>(in, it.qblock, it.slice, tiles, norms, bufs);
+      if (two) wide_item<KIND, 8, 2, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
+      else wide_item<KIND, 8, 1, 2>(in, it.qblock, it.slice, tiles, norms, bufs);
       break;
   }
 }
 
-// The instantiation with the shared-bound code serves item launches and
-// single searches whose slices share a bound; single searches of one slice
-// per query take the one without it (which runs faster: fewer registers).
+// Item launches take the instantiation with both shared bounds; a single
+// search takes the one its bounds call for (one slice per query: none, which
+// runs fastest; fewer than kRankMinSlices slices: the kc-th best alone, as
+// the rank code costs registers there for little gain).
 template <int KIND, int NKG>
 hipError_t launch_wide_one(const FusedParams& p, hipStream_t stream) {
   if (p.items && p.nitems <= 0) return hipSuccess;
   dim3 grid = p.items ? dim3((unsigned)p.nitems)
                       : dim3((unsigned)((p.one.n + kWideQueriesWG - 1) / kWideQueriesWG), (unsigned)p.one.P);
-  const bool share = p.items != nullptr || p.one.tshare != nullptr;
+  const int share = p.items ? 2 : !p.one.tshare ? 0 : p.one.rank_r > 0 ? 2 : 1;
   const dim3 block(kWideWaves * kWaveSize);
   if constexpr (KIND != TILE_L2_F32) {
     if (p.kc_max > kWideMaxKc1) {
-      if (share) hipLaunchKernelGGL((wide2_kernel<KIND, NKG, true>), grid, block, 0, stream, p);
-      else hipLaunchKernelGGL((wide2_kernel<KIND, NKG, false>), grid, block, 0, stream, p);
+      if (share == 2) hipLaunchKernelGGL((wide2_kernel<KIND, NKG, 2>), grid, block, 0, stream, p);
+      else if (share == 1) hipLaunchKernelGGL((wide2_kernel<KIND, NKG, 1>), grid, block, 0, stream, p);
+      else hipLaunchKernelGGL((wide2_kernel<KIND, NKG, 0>), grid, block, 0, stream, p);
       return hipGetLastError();
     }
   }
-  if (share) hipLaunchKernelGGL((wide_kernel<KIND, NKG, true>), grid, block, 0, stream, p);
-  else hipLaunchKernelGGL((wide_kernel<KIND, NKG, false>), grid, block, 0, stream, p);
+  if (share == 2) hipLaunchKernelGGL((wide_kernel<KIND, NKG, 2>), grid, block, 0, stream, p);
+  else if (share == 1) hipLaunchKernelGGL((wide_kernel<KIND, NKG, 1>), grid, block, 0, stream, p);
+  else hipLaunchKernelGGL((wide_kernel<KIND, NKG, 0>), grid, block, 0, stream, p);
   return hipGetLastError();
+}
+
+// launch_wide_one for the padded widths of a 16-bit tile kind (p.ng k groups)
+template <int KIND>
+hipError_t dispatch_half(const FusedParams& p, hipStream_t stream) {
+  switch (p.ng) {
+    case 2: return launch_wide_one<KIND, 2>(p, stream);
+    case 4: return launch_wide_one<KIND, 4>(p, stream);
+    case 6: return launch_wide_one<KIND, 6>(p, stream);
+    case 8: return launch_wide_one<KIND, 8>(p, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int KIND>

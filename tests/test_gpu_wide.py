@@ -205,23 +205,31 @@ def test_wide_two_keys_integer_grid_is_exact(K, prec):
     assert np.array_equal(dist, D.astype(np.float32))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
-def test_wide_slices_sharing_a_bound_equal_one_slice(K, prec):
+@pytest.mark.parametrize("prec,k", [("bf16", 32), ("fp16", 32), ("bf16", 90)])
+def test_wide_slices_sharing_a_bound_equal_one_slice(K, prec, k):
     """Slices of one query publish their k'-th best and filter with the
-    smallest any of them has published.  That bound drops only candidates that
-    cannot be among the query's k' best of the whole set, so 1, 16, 64 and 256
-    slices (KNN_FUSED_P) must give bitwise the same result."""
-    banner(f"wide shared bound {prec}")
+    smallest any of them has published; from 8 slices on they also publish
+    their r-th best (r = ceil(k' / P)) and filter with the smallest, over
+    groups of ceil(k' / r) slices, of the largest value in a group.  Both
+    bounds drop only candidates that cannot be among the query's k' best of
+    the whole set, so any number of slices (KNN_FUSED_P; the last slice
+    shorter), with or without the rank bound (KNN_RANK_SHARE=0), must give
+    bitwise the same result as one slice.  k = 90 (k' = 122) takes two list
+    keys per lane, and at most 2048 / k' = 16 slices."""
+    banner(f"wide shared bound {prec} k={k}")
     Q, R = data("gmm", 300, 200000, 64, 811)
-    k = 32
     out = {}
-    for P in (1, 16, 64, 256):
+    runs = [(1, "1"), (4, "1"), (8, "1"), (16, "1"), (64, "1"), (64, "0"), (256, "1")]
+    for P, rank in runs:
         os.environ["KNN_FUSED_P"] = str(P)
+        os.environ["KNN_RANK_SHARE"] = rank
         try:
-            out[P] = search16(K, Q, R, k, prec)
+            out[(P, rank)] = search16(K, Q, R, k, prec)
         finally:
             del os.environ["KNN_FUSED_P"]
-    check(Q, R, k, *out[1])
-    for P in (16, 64, 256):
-        assert np.array_equal(out[P][1], out[1][1]), f"indices differ with {P} slices"
-        assert np.array_equal(out[P][0].view(np.uint32), out[1][0].view(np.uint32)), f"distances differ with {P} slices"
+            del os.environ["KNN_RANK_SHARE"]
+    check(Q, R, k, *out[(1, "1")])
+    for key in runs[1:]:
+        assert np.array_equal(out[key][1], out[(1, "1")][1]), f"indices differ with {key[0]} slices (rank {key[1]})"
+        assert np.array_equal(out[key][0].view(np.uint32), out[(1, "1")][0].view(np.uint32)), \
+            f"distances differ with {key[0]} slices (rank {key[1]})"
