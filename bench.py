@@ -45,7 +45,7 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 # rates measured on one MI355X by `bench.py --mode peaks` (profiles/peaks_mi355x.md)
 MEASURED_FP32_MFMA_TFLOPS = 155.3
-MEASURED_BF16_MFMA_TFLOPS = 2170.8
+MEASURED_BF16_MFMA_TFLOPS = 2231.4
 MEASURED_VALU_TOPS = 41.78
 
 WORKLOAD_METRICS = {
