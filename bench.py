@@ -43,6 +43,10 @@ PEAK_BF16_MFMA_TFLOPS = 2516.6
 # 256 CUs x 64 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
+# LDS reads taken at 256 bytes per CU per clock, 256 CUs, 2.4 GHz: not a
+# datasheet figure; the measured 16-byte read rate (228 bytes per CU per clock,
+# profiles/peaks_mi355x.md) exceeds the 128 of the previous generation
+PEAK_LDS_TBS = 256 * 256 * 2.4e9 / 1e12
 # rates measured on one MI355X by `bench.py --mode peaks` (profiles/peaks_mi355x.md)
 MEASURED_FP32_MFMA_TFLOPS = 155.3
 MEASURED_BF16_MFMA_TFLOPS = 2231.4
@@ -812,8 +816,9 @@ def bench_copy(args):
 def bench_peaks(args):
     """Measured issue rates of the instructions the roofline peaks assume:
     the Manhattan kernel's vector subtract (DPP operand) + absolute add, the
-    BF16 32x32x16 and float32 32x32x2 matrix instructions; each with the
-    shader clock of the run (s_memtime against the 100 MHz s_memrealtime)."""
+    BF16 32x32x16 and float32 32x32x2 matrix instructions, and 16-byte LDS
+    reads; each with the shader clock of the run (s_memtime against the
+    100 MHz s_memrealtime)."""
     import ctypes
 
     import torch
@@ -828,7 +833,8 @@ def bench_peaks(args):
     # (name, which, workgroups of 4 waves, iterations, work per wave and iteration, unit, datasheet peak)
     cases = [("valu_sub_dpp_absadd", 0, cus * 8, 20000, 64 * 16, "T lane-ops/s", PEAK_VALU_TOPS),
              ("mfma_bf16_32x32x16", 1, cus * 8, 10000, 8 * 32768, "TFLOP/s", PEAK_BF16_MFMA_TFLOPS),
-             ("mfma_f32_32x32x2", 2, cus * 8, 10000, 8 * 4096, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS)]
+             ("mfma_f32_32x32x2", 2, cus * 8, 10000, 8 * 4096, "TFLOP/s", PEAK_FP32_MFMA_TFLOPS),
+             ("lds_read_b128", 3, cus * 4, 20000, 8 * 1024, "TB/s", PEAK_LDS_TBS)]
     stream = torch.cuda.current_stream()
     out = {}
     for name, which, blocks, iters, per_wave, unit, peak in cases:

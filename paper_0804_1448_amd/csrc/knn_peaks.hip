@@ -1,8 +1,8 @@
 // knn_peaks.hip -- micro-benchmarks that measure the issue rates the
 // roofline fractions of the k-NN kernels are taken against: the vector ALU
 // rate of the Manhattan kernel's inner operations, the float32 and BF16
-// matrix-core rates of the Euclidean kernels, and the shader clock they ran
-// at.  Built as its own library (libknn_peaks.so), used by the benchmark
+// matrix-core rates of the Euclidean kernels, the LDS read rate their
+// operand reads draw on, and the shader clock they ran at.  Built as its own library (libknn_peaks.so), used by the benchmark
 // only; not part of the k-NN C ABI.
 //
 // Every kernel runs `iters` iterations of independent instruction chains on
@@ -142,6 +142,37 @@ __global__ __launch_bounds__(256) void mfma_chains_kernel(float* out, uint64_t* 
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// ds_read_b128 rate: per iteration each wave reads eight consecutive 1 KB
+// blocks of a 32 KB LDS buffer, lane l the l-th 16-byte chunk of a block
+// (the access of the 32x32 kernel's operand reads, without bank conflicts);
+// the eight reads share one address register and differ by their immediate
+// offsets.  The words read are summed into one value (two v_add3_u32 per
+// read) so that every read stays live; the first block steps by 3 (mod 16)
+// per iteration, so no unrolled copy of the loop repeats an address, and
+// `rot`, taken from a launch argument, keeps the sequence from being known at
+// compile time.  32 KB per workgroup: at most four
+// workgroups (16 waves) per CU.
+__global__ __launch_bounds__(256) void lds_read_kernel(float* out, uint64_t* clk, int iters, float seed) {
+  __shared__ __align__(16) uint4 buf[2048];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const uint32_t sb = __float_as_uint(seed);
+  for (int i = t; i < 2048; i += 256) buf[i] = make_uint4(i, i * 3u, i * 5u, (i * 7u) ^ sb);
+  __syncthreads();
+  const int rot = (int)(sb & 15u);
+  uint32_t acc = 0;
+  stamp(clk, 0);
+  for (int it = 0; it < iters; ++it) {
+    const uint4* p = buf + ((it * 3 + wave + rot) & 15) * 64 + lane;  // blocks 0..22 of 32
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint4 v = p[u * 64];
+      acc = acc + v.x + v.y + v.z + v.w;
+    }
+  }
+  stamp(clk, 1);
+  out[blockIdx.x * blockDim.x + threadIdx.x] = __uint_as_float(acc);
+}
+
 }  // namespace
 
 extern "C" {
@@ -163,12 +194,13 @@ int knn_peak_launch_chains(int chains, int blocks, int iters, float* out, uint64
 }
 
 // Launch micro-benchmark `which` (0 vector ALU, 1 BF16 matrix, 2 float32
-// matrix) with `blocks` workgroups of 256 lanes, `iters` iterations each, on
-// `stream`.  out: device float [blocks * 256]; clk: device uint64 [4]
-// (shader-clock and 100 MHz counters before and after the loop of workgroup
-// 0).  Work per launch, per lane and iteration: 16 vector operations (8
-// subtractions + 8 absolute adds); 8 * 32768 BF16 flops per wave; 8 * 4096
-// float32 flops per wave.  Returns the HIP status of the launch.
+// matrix, 3 LDS reads) with `blocks` workgroups of 256 lanes, `iters`
+// iterations each, on `stream`.  out: device float [blocks * 256]; clk:
+// device uint64 [4] (shader-clock and 100 MHz counters before and after the
+// loop of workgroup 0).  Work per launch, per lane and iteration: 16 vector
+// operations (8 subtractions + 8 absolute adds); 8 * 32768 BF16 flops per
+// wave; 8 * 4096 float32 flops per wave; 8 * 1024 bytes read from LDS per
+// wave.  Returns the HIP status of the launch.
 int knn_peak_launch(int which, int blocks, int iters, float* out, uint64_t* clk, void* stream) {
   if (blocks < 1 || iters < 1 || !out || !clk) return (int)hipErrorInvalidValue;
   const hipStream_t s = (hipStream_t)stream;
@@ -177,6 +209,7 @@ int knn_peak_launch(int which, int blocks, int iters, float* out, uint64_t* clk,
     case 0: hipLaunchKernelGGL(valu_kernel, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
     case 1: hipLaunchKernelGGL(mfma_bf16_kernel, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
     case 2: hipLaunchKernelGGL(mfma_f32_kernel, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
+    case 3: hipLaunchKernelGGL(lds_read_kernel, dim3(blocks), dim3(256), 0, s, out, clk, iters, seed); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
