@@ -249,7 +249,11 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       const int cnt1 = __builtin_amdgcn_readlane(lcnt, j + 32);
       const int e = lane & 31;
       const uint64_t* sp = wbufs + (size_t)(j + 32 * h) * SEG;
-      uint64_t x = e < (h ? cnt1 : cnt0) ? sp[e] : kEmptyKey;
+      uint64_t x = kEmptyKey;
+      if (e < (h ? cnt1 : cnt0)) {  // a buffered key: float bits of the score, mapped here
+        const uint64_t r = sp[e];
+        x = ((uint64_t)mono_code(__uint_as_float((uint32_t)(r >> 32))) << 32) | (uint32_t)r;
+      }
       const uint64_t l = ((uint64_t)Lhi[j] << 32) | Llo[j];
       x = bitonic_sort64(x, lane, true);
       uint64_t m = l < x ? l : x;
@@ -382,15 +386,20 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
         const uint32_t qm = (uint32_t)(ov | (ov >> 32));
         if (qm) merge_queries(qm);
         const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
+        // branch-free appends: every score of a group with a candidate in the
+        // wave is stored at the lane's count, which advances only for the
+        // scores that pass (a failing one is overwritten or lies past the
+        // count; the index stays at most SUB < SEG).  The high word holds the
+        // score's float bits; the merge maps them to the monotone code.
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (!ballot(mq[q] <= thr)) continue;  // no candidate in this group anywhere in the wave
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (acc[t][4 * q + i] <= thr) {
-              myseg[lcnt] = make_key(acc[t][4 * q + i], rref + (uint32_t)(8 * q + i));
-              ++lcnt;
-            }
+          for (int i = 0; i < 4; ++i) {
+            const float v = acc[t][4 * q + i];
+            myseg[lcnt] = ((uint64_t)__float_as_uint(v) << 32) | (rref + (uint32_t)(8 * q + i));
+            lcnt += v <= thr ? 1 : 0;
+          }
         }
       }
     }
