@@ -170,9 +170,13 @@ __device__ __forceinline__ void merge_ranked(uint64_t* L, const Segs& b, int len
 // to v leaves v's even 16-lane rows in the first result and its odd rows in
 // the second, each row duplicated over its pair; v_permlane32_swap does the
 // same for 32-lane halves.  A lane then takes the copy of its partner row.
+// Every lane reads a lane of its own row (quad permutes, row rotate), or, for
+// the row shifts, a lane whose value the caller discards where the shift
+// leaves the row; so no "old" value is needed (bound control: such lanes read
+// zero), which saves the move that would initialize one.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
 template <int J>
