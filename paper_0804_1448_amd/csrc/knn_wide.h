@@ -247,15 +247,19 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       qm &= qm - 1;
       const int cnt0 = __builtin_amdgcn_readlane(lcnt, j);
       const int cnt1 = __builtin_amdgcn_readlane(lcnt, j + 32);
-      const int e = lane & 31;
-      const uint64_t* sp = wbufs + (size_t)(j + 32 * h) * SEG;
+      // the buffered keys of the query's two lanes (float bits of the score,
+      // mapped here), sorted descending over the wave
+      const uint64_t* sp0 = wbufs + (size_t)j * SEG;
+      const uint64_t* sp1 = wbufs + (size_t)(j + 32) * SEG;
+      auto key_at = [](const uint64_t* p, int i) __attribute__((always_inline)) {
+        const uint64_t r = p[i];
+        return ((uint64_t)mono_code(__uint_as_float((uint32_t)(r >> 32))) << 32) | (uint32_t)r;
+      };
       uint64_t x = kEmptyKey;
-      if (e < (h ? cnt1 : cnt0)) {  // a buffered key: float bits of the score, mapped here
-        const uint64_t r = sp[e];
-        x = ((uint64_t)mono_code(__uint_as_float((uint32_t)(r >> 32))) << 32) | (uint32_t)r;
-      }
-      const uint64_t l = ((uint64_t)Lhi[j] << 32) | Llo[j];
+      const int e = lane & 31;
+      if (e < (h ? cnt1 : cnt0)) x = key_at(h ? sp1 : sp0, e);
       x = bitonic_sort64(x, lane, true);
+      const uint64_t l = ((uint64_t)Lhi[j] << 32) | Llo[j];
       uint64_t m = l < x ? l : x;
       uint32_t kth;
       if constexpr (LK == 1) {
