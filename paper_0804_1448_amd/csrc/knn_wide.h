@@ -361,11 +361,11 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
     __builtin_amdgcn_s_setprio(0);
   };
 
-  // ---- selection phase over the scores of step `st` (in acc).  Before a
-  // tile's candidates are appended, a lane whose segment might overflow has
-  // its query merged; the bound on the lane's new keys is 4 per group of 4
-  // scores whose minimum passes the threshold (the group minima also give
-  // the tile minimum that decides whether the tile has a candidate at all).
+  // ---- selection phase over the scores of step `st` (in acc).  The minima
+  // of the tile's groups of 4 scores decide whether the tile, and then each
+  // group, has a candidate anywhere in the wave; a group's candidates are
+  // appended after the lanes whose segments cannot take them have had their
+  // queries merged.
   auto select = [&](int st) __attribute__((always_inline)) {
     const int64_t tb = s0 + (int64_t)st * kStepRefs;
     if (tb + kStepRefs > s1) {  // last, partial step of the slice
@@ -385,19 +385,24 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
                          acc[t][4 * q + 3]);
       const float mn = min3_raw(min3_raw(mq[0], mq[1], mq[2]), mq[3], mq[3]);
       if (ballot(mn <= thr)) {
-        const int bound = 4 * ((mq[0] <= thr) + (mq[1] <= thr) + (mq[2] <= thr) + (mq[3] <= thr));
-        const uint64_t ov = ballot(lcnt + bound > SUB);
-        const uint32_t qm = (uint32_t)(ov | (ov >> 32));
-        if (qm) merge_queries(qm);
         const uint32_t rref = (uint32_t)(tb + 32 * t + 4 * h);
-        // branch-free appends: every score of a group with a candidate in the
-        // wave is stored at the lane's count, which advances only for the
-        // scores that pass (a failing one is overwritten or lies past the
-        // count; the index stays at most SUB < SEG).  The high word holds the
-        // score's float bits; the merge maps them to the monotone code.
+        // Per group of 4 scores with a candidate in the wave: a lane whose
+        // buffer cannot take its passing scores has its query merged first
+        // (so buffers fill to SUB keys before a merge), then branch-free
+        // appends: every score is stored at the lane's count, which advances
+        // only for the scores that pass (a failing one is overwritten or lies
+        // past the count; the index stays at most SUB < SEG).  The high word
+        // holds the score's float bits; the merge maps them to the monotone
+        // code.  A merge only lowers the threshold, so the count taken before
+        // it bounds the keys appended after it.
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (!ballot(mq[q] <= thr)) continue;  // no candidate in this group anywhere in the wave
+          const int np = (acc[t][4 * q] <= thr) + (acc[t][4 * q + 1] <= thr) + (acc[t][4 * q + 2] <= thr) +
+                         (acc[t][4 * q + 3] <= thr);
+          const uint64_t ov = ballot(lcnt + np > SUB);
+          const uint32_t qm = (uint32_t)(ov | (ov >> 32));
+          if (qm) merge_queries(qm);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const float v = acc[t][4 * q + i];
