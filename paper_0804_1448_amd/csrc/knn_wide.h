@@ -436,7 +436,13 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
   }
   int bs = 0;   // tile buffer of `step`
   int gi = 0;   // position of `step` in its group
-  for (int step = 0; step <= nsteps; ++step) {
+  // A wave whose 32 query rows all lie past n (the last query block of a
+  // small search) skips this loop: see the one after it.  Only the kernels
+  // with rank slots (many slices per query, and every item launch) carry that
+  // path: the others keep the plain loop, whose schedule it would change.
+  const bool live = SHARE < 2 || __builtin_amdgcn_readfirstlane((int)(q0 < in.n));
+  const int last = live ? nsteps : -1;
+  for (int step = 0; step <= last; ++step) {
     if (gi == 0 && step < nsteps) {
       // group start: stage the next group into the other half of the buffers
 #pragma unroll
@@ -476,6 +482,24 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
     }
     bs = bs == STAGES - 1 ? 0 : bs + 1;
     gi = gi == GRP - 1 ? 0 : gi + 1;
+  }
+  if (!live) {
+    // Such a wave only issues its share of the copies and takes the same
+    // barriers, so the other wave on its SIMD has the matrix cores and vector
+    // ALUs to itself.  Its lists stay empty and are not written.
+    int db = 0, dg = 0;
+    for (int step = 0; step < nsteps; ++step) {
+      if (dg == 0) {
+#pragma unroll
+        for (int i = 0; i < GRP; ++i) stage(min(step + GRP + i, nsteps - 1), (db ^ GRP) + i);
+      }
+      if (dg == GRP - 1 || step == nsteps - 1) {
+        wait_vmem();
+        barrier_keep_copies();
+      }
+      db = db == STAGES - 1 ? 0 : db + 1;
+      dg = dg == GRP - 1 ? 0 : dg + 1;
+    }
   }
   {  // end of the slice: flush every buffer
     const uint64_t pend = ballot(lcnt > 0);
