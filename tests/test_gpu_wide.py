@@ -233,3 +233,25 @@ def test_wide_slices_sharing_a_bound_equal_one_slice(K, prec, k):
         assert np.array_equal(out[key][1], out[(1, "1")][1]), f"indices differ with {key[0]} slices (rank {key[1]})"
         assert np.array_equal(out[key][0].view(np.uint32), out[(1, "1")][0].view(np.uint32)), \
             f"distances differ with {key[0]} slices (rank {key[1]})"
+
+
+@pytest.mark.parametrize("n", [1, 33, 224])
+def test_wide_small_search_with_empty_waves(K, n):
+    """A search of fewer than 256 queries fills one query block only in part.
+    From 8 slices on (the kernels with rank slots) a wave whose 32 rows all
+    lie past n only copies tiles and takes the barriers: n = 1 leaves seven
+    such waves, n = 33 six, n = 224 one (the last).  The live rows must match
+    the oracle and, bitwise, the one-slice search, which has no such path."""
+    banner(f"wide small search n={n}")
+    Q, R = data("gmm", n, 100000, 64, 907)
+    out = {}
+    for P in (1, 16, 64):
+        os.environ["KNN_FUSED_P"] = str(P)
+        try:
+            out[P] = search16(K, Q, R, 32, "fp16")
+        finally:
+            del os.environ["KNN_FUSED_P"]
+    check(Q, R, 32, *out[1])
+    for P in (16, 64):
+        assert np.array_equal(out[P][1], out[1][1]), f"indices differ with {P} slices"
+        assert np.array_equal(out[P][0].view(np.uint32), out[1][0].view(np.uint32)), f"distances differ with {P} slices"
