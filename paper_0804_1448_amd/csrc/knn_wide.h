@@ -203,7 +203,9 @@ __device__ __forceinline__ void wide_item(const FusedInst& in, int qblock, int s
       Lhi2[j] = 0xffffffffu;
     }
   }
-  float thr = __builtin_huge_valf();
+  // A lane whose row lies past n admits nothing (in the kernels with rank
+  // slots, which serve the small searches; the others keep the plain start).
+  float thr = SHARE == 2 && qrow >= in.n ? -__builtin_huge_valf() : __builtin_huge_valf();
   int lcnt = 0;
   uint64_t* myseg = bufs + (size_t)(wave * 64 + lane) * SEG;
   const uint64_t* wbufs = bufs + (size_t)wave * 64 * SEG;
